@@ -1,0 +1,99 @@
+// Internal types shared by the host runtime and the HIP kernels of liblkmi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <cstdint>
+
+#include "lk.h"
+
+namespace lkmi {
+
+// One pyramid level as the kernels see it.  Level 0 is the caller's 8-bit
+// frame; levels >= 1 are float (LK_STORAGE_F32) or binary16 (LK_STORAGE_F16).
+// For LK_STORAGE_F16 every level also has a (Gx, Gy) binary16 plane.
+struct LevelDesc {
+    const void *img;
+    const __half2 *grad;   // nullptr for LK_STORAGE_F32
+    int32_t pitch;         // elements per row of img
+    int32_t gpitch;        // half2 elements per row of grad
+    int32_t w, h;
+};
+
+struct PyrDesc {
+    LevelDesc lv[LK_MAX_LEVELS];
+    int32_t levels;
+    int32_t storage;
+};
+
+struct TrackArgs {
+    int32_t win, levels, max_iters, use_guess;
+    float eps, min_eig, fb_thresh;
+    int32_t n;                 // points (plain launch) or total points (batched)
+    const float *pts;
+    const float *guess;
+    float *out_pts;
+    uint8_t *status;
+    float *residual;
+    int32_t *iters;
+};
+
+// Item of a batched launch: points [pt_offset, pt_offset + n).  The
+// descriptors live in device memory (each pyramid keeps its own).
+struct BatchItem {
+    const PyrDesc *prev;
+    const PyrDesc *next;
+    int64_t pt_offset;
+    int32_t n;
+    int32_t first_wave;        // prefix sum of n over earlier items
+};
+
+// A descriptor to be copied to device memory by k_write_descs.
+struct PyrDescWrite {
+    PyrDesc *dst;
+    PyrDesc desc;
+};
+
+// One pyramid step (level l-1 -> level l) of one frame, tiled.
+struct DownJob {
+    const void *src;
+    void *dst;
+    int32_t spitch, dpitch;    // elements per row
+    int32_t sw, sh, dw, dh;
+    int32_t src_u8;            // source is the 8-bit level 0
+    int32_t dst_f16;           // destination stored as binary16
+    int32_t tiles_x, tile_begin;
+};
+
+// Gradient plane of one level of one frame (LK_STORAGE_F16 only).
+struct GradJob {
+    const void *src;
+    __half2 *dst;
+    int32_t spitch, dpitch;
+    int32_t w, h;
+    int32_t src_u8;
+    int32_t tiles_x, tile_begin;
+};
+
+// Tile shapes of the pyramid kernels.
+constexpr int kDownTileW = 64, kDownTileH = 16;
+constexpr int kGradTileW = 64, kGradTileH = 16;
+
+// Window-to-lane layouts of the tracker (see lk_kernels.hip).
+enum Layout { LAYOUT_W21 = 0, LAYOUT_W31 = 1, LAYOUT_W63 = 2 };
+int choose_layout(int win);
+
+// Launchers (lk_kernels.hip).  All enqueue on `stream` and return the launch status.
+hipError_t launch_downsample(const DownJob &job, hipStream_t stream);
+hipError_t launch_downsample_batched(const DownJob *d_jobs, int njobs, int total_tiles, hipStream_t stream);
+hipError_t launch_grad(const GradJob &job, hipStream_t stream);
+hipError_t launch_grad_batched(const GradJob *d_jobs, int njobs, int total_tiles, hipStream_t stream);
+hipError_t launch_track(const PyrDesc *d_prev, const PyrDesc *d_next, int storage, const TrackArgs &a,
+                        hipStream_t stream);
+hipError_t launch_write_desc(PyrDesc *d_dst, const PyrDesc &src, hipStream_t stream);
+hipError_t launch_write_descs(const PyrDescWrite *d_w, int n, hipStream_t stream);
+hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total_points,
+                                const TrackArgs &a, int storage, hipStream_t stream);
+hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream);
+
+}  // namespace lkmi

@@ -1,0 +1,500 @@
+// Host runtime of liblkmi: contexts, pyramid objects, argument checks, the
+// C ABI of lk.h, and the staging of batch tables.
+#include "lk_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lkmi;
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace lkmi {
+
+lk_result fail(lk_result code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+lk_result hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? LK_ERR_OUT_OF_MEMORY : LK_ERR_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// ------------------------------------------------------------------ staging
+
+lk_result StagingRing::init(int nslots)
+{
+    slots.resize(nslots);
+    for (auto &s : slots) {
+        hipError_t e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    return LK_SUCCESS;
+}
+
+void StagingRing::release()
+{
+    for (auto &s : slots) {
+        if (s.done) (void)hipEventSynchronize(s.done);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.done) (void)hipEventDestroy(s.done);
+        s = Slot{};
+    }
+}
+
+lk_result StagingRing::acquire(size_t bytes, Slot **out)
+{
+    Slot &s = slots[next];
+    next = (next + 1) % (int)slots.size();
+    hipError_t e = hipEventSynchronize(s.done);   // previous user of this slot has finished
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    if (bytes > s.cap) {
+        size_t cap = std::max<size_t>(bytes, 2 * s.cap);
+        cap = (cap + 4095) & ~size_t(4095);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        s.host = nullptr; s.dev = nullptr; s.cap = 0;
+        e = hipHostMalloc(&s.host, cap, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+        e = hipMalloc(&s.dev, cap);
+        if (e != hipSuccess) { (void)hipHostFree(s.host); s.host = nullptr; return hip_fail(e, "hipMalloc"); }
+        s.cap = cap;
+    }
+    *out = &s;
+    return LK_SUCCESS;
+}
+
+// ------------------------------------------------------------------ checks
+
+int level_dims(int w, int h, int levels, int32_t *ws, int32_t *hs)
+{
+    if (levels < 1 || levels > LK_MAX_LEVELS || w < 1 || h < 1) return -1;
+    ws[0] = w; hs[0] = h;
+    for (int l = 1; l < levels; ++l) {
+        ws[l] = (ws[l - 1] + 1) / 2;
+        hs[l] = (hs[l - 1] + 1) / 2;
+    }
+    return (ws[levels - 1] >= 4 && hs[levels - 1] >= 4) ? 0 : -1;
+}
+
+lk_result check_params(const lk_params *p, int pyr_levels)
+{
+    if (!p) return fail(LK_ERR_INVALID_ARG, "params is NULL");
+    if (p->win < 3 || p->win > 63 || (p->win & 1) == 0)
+        return fail(LK_ERR_INVALID_ARG, "win must be odd in [3, 63] (got %d)", p->win);
+    if (p->levels < 1 || p->levels > pyr_levels)
+        return fail(LK_ERR_INVALID_ARG, "levels must be in [1, %d] (got %d)", pyr_levels, p->levels);
+    if (p->max_iters < 1 || p->max_iters > 1000)
+        return fail(LK_ERR_INVALID_ARG, "max_iters must be in [1, 1000] (got %d)", p->max_iters);
+    if (!(p->eps > 0.0f) || !std::isfinite(p->eps)) return fail(LK_ERR_INVALID_ARG, "eps must be > 0");
+    if (!(p->min_eig >= 0.0f) || !std::isfinite(p->min_eig)) return fail(LK_ERR_INVALID_ARG, "min_eig must be >= 0");
+    if (!(p->fb_thresh >= 0.0f) || !std::isfinite(p->fb_thresh))
+        return fail(LK_ERR_INVALID_ARG, "fb_thresh must be >= 0");
+    if (p->use_guess != 0 && p->use_guess != 1) return fail(LK_ERR_INVALID_ARG, "use_guess must be 0 or 1");
+    if (p->reserved != 0) return fail(LK_ERR_INVALID_ARG, "reserved must be 0");
+    return LK_SUCCESS;
+}
+
+TrackArgs make_args(const lk_params *p, int n, const float *pts, const float *guess, float *out, uint8_t *st,
+                    float *res, int32_t *iters)
+{
+    TrackArgs a;
+    a.win = p->win; a.levels = p->levels; a.max_iters = p->max_iters; a.use_guess = p->use_guess;
+    a.eps = p->eps; a.min_eig = p->min_eig; a.fb_thresh = p->fb_thresh;
+    a.n = n; a.pts = pts; a.guess = p->use_guess ? guess : nullptr;
+    a.out_pts = out; a.status = st; a.residual = res; a.iters = iters;
+    return a;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Down/grad jobs that build one pyramid from its recorded level 0.
+void pyramid_jobs(const lk_pyramid *p, std::vector<DownJob> *down_by_level, std::vector<GradJob> *grads)
+{
+    const PyrDesc &d = p->desc;
+    for (int l = 1; l < d.levels; ++l) {
+        DownJob j{};
+        j.src = d.lv[l - 1].img; j.dst = const_cast<void *>(d.lv[l].img);
+        j.spitch = d.lv[l - 1].pitch; j.dpitch = d.lv[l].pitch;
+        j.sw = d.lv[l - 1].w; j.sh = d.lv[l - 1].h; j.dw = d.lv[l].w; j.dh = d.lv[l].h;
+        j.src_u8 = l == 1; j.dst_f16 = d.storage == LK_STORAGE_F16;
+        j.tiles_x = (j.dw + kDownTileW - 1) / kDownTileW;
+        j.tile_begin = 0;
+        down_by_level[l].push_back(j);
+    }
+    if (d.storage == LK_STORAGE_F16)
+        for (int l = 0; l < d.levels; ++l) {
+            GradJob g{};
+            g.src = d.lv[l].img; g.dst = const_cast<__half2 *>(d.lv[l].grad);
+            g.spitch = d.lv[l].pitch; g.dpitch = d.lv[l].gpitch;
+            g.w = d.lv[l].w; g.h = d.lv[l].h; g.src_u8 = l == 0;
+            g.tiles_x = (g.w + kGradTileW - 1) / kGradTileW;
+            g.tile_begin = 0;
+            grads->push_back(g);
+        }
+}
+
+}  // namespace lkmi
+
+// ====================================================================== ABI
+
+extern "C" {
+
+lk_params lk_params_default(void)
+{
+    lk_params p;
+    p.win = 21; p.levels = 3; p.max_iters = 30; p.use_guess = 0;
+    p.eps = 0.01f; p.min_eig = 1e-6f; p.fb_thresh = 0.0f; p.reserved = 0;
+    return p;
+}
+
+const char *lk_last_error(void) { return g_last_error.c_str(); }
+
+lk_result lk_context_create(int32_t device, uint64_t hbm_budget_bytes, lk_context **out)
+{
+    if (!out) return fail(LK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(LK_ERR_INVALID_ARG, "device %d not in [0, %d)", device, count);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    lk_context *c = new (std::nothrow) lk_context();
+    if (!c) return fail(LK_ERR_OUT_OF_MEMORY, "host allocation failed");
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    lk_result r = c->staging.init(8);
+    if (r != LK_SUCCESS) { delete c; return r; }
+    *out = c;
+    clear_error();
+    return LK_SUCCESS;
+}
+
+void lk_context_destroy(lk_context *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->graphs_release();
+    ctx->staging.release();
+    delete ctx;
+}
+
+uint64_t lk_context_bytes_in_use(const lk_context *ctx) { return ctx ? ctx->in_use.load() : 0; }
+
+lk_result lk_pyramid_create(lk_context *ctx, int32_t w, int32_t h, int32_t levels, int32_t storage, lk_pyramid **out)
+{
+    if (!ctx || !out) return fail(LK_ERR_INVALID_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    if (storage != LK_STORAGE_F32 && storage != LK_STORAGE_F16)
+        return fail(LK_ERR_INVALID_ARG, "storage must be LK_STORAGE_F32 or LK_STORAGE_F16");
+    int32_t ws[LK_MAX_LEVELS], hs[LK_MAX_LEVELS];
+    if (w > (1 << 15) || h > (1 << 15) || level_dims(w, h, levels, ws, hs) != 0)
+        return fail(LK_ERR_INVALID_ARG, "bad pyramid shape %dx%d with %d levels (1..8 levels, coarsest >= 4x4, "
+                    "sides <= 32768)", w, h, levels);
+    lk_pyramid *p = new (std::nothrow) lk_pyramid();
+    if (!p) return fail(LK_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->ctx = ctx;
+    PyrDesc &d = p->desc;
+    std::memset(&d, 0, sizeof d);
+    d.levels = levels;
+    d.storage = storage;
+    const size_t es = storage == LK_STORAGE_F16 ? 2 : 4;
+    size_t off[LK_MAX_LEVELS] = {0}, goff[LK_MAX_LEVELS] = {0};
+    size_t total = align_up(sizeof(PyrDesc), 256);   // the device copy of the descriptor comes first
+    for (int l = 0; l < levels; ++l) {
+        d.lv[l].w = ws[l]; d.lv[l].h = hs[l];
+        if (l > 0) {
+            d.lv[l].pitch = (int32_t)align_up(ws[l], 256 / es);
+            off[l] = total;
+            total = align_up(total + (size_t)d.lv[l].pitch * hs[l] * es, 256);
+        }
+        if (storage == LK_STORAGE_F16) {
+            d.lv[l].gpitch = (int32_t)align_up(ws[l], 64);
+            goff[l] = total;
+            total = align_up(total + (size_t)d.lv[l].gpitch * hs[l] * 4, 256);
+        }
+    }
+    if (ctx->budget && ctx->in_use.load() + total > ctx->budget) {
+        delete p;
+        return fail(LK_ERR_OUT_OF_MEMORY, "pyramid of %zu bytes exceeds the context budget", total);
+    }
+    (void)hipSetDevice(ctx->device);
+    {
+        hipError_t e = hipMalloc(&p->base, total);
+        if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(pyramid)"); }
+    }
+    p->bytes = total;
+    ctx->in_use += total;
+    char *b = static_cast<char *>(p->base);
+    p->d_desc = reinterpret_cast<PyrDesc *>(b);
+    for (int l = 0; l < levels; ++l) {
+        if (l > 0) d.lv[l].img = b + off[l];
+        if (storage == LK_STORAGE_F16) d.lv[l].grad = reinterpret_cast<const __half2 *>(b + goff[l]);
+    }
+    *out = p;
+    return LK_SUCCESS;
+}
+
+lk_result lk_pyramid_destroy(lk_pyramid *pyr)
+{
+    if (!pyr) return fail(LK_ERR_INVALID_ARG, "pyr is NULL");
+    if (pyr->base) {
+        (void)hipSetDevice(pyr->ctx->device);
+        hipError_t e = hipFree(pyr->base);
+        pyr->ctx->in_use -= pyr->bytes;
+        delete pyr;
+        if (e != hipSuccess) return hip_fail(e, "hipFree(pyramid)");
+        return LK_SUCCESS;
+    }
+    delete pyr;
+    return LK_SUCCESS;
+}
+
+lk_result lk_pyramid_info(const lk_pyramid *pyr, int32_t *w, int32_t *h, int32_t *levels, int32_t *storage)
+{
+    if (!pyr) return fail(LK_ERR_INVALID_ARG, "pyr is NULL");
+    if (w) *w = pyr->desc.lv[0].w;
+    if (h) *h = pyr->desc.lv[0].h;
+    if (levels) *levels = pyr->desc.levels;
+    if (storage) *storage = pyr->desc.storage;
+    return LK_SUCCESS;
+}
+
+lk_result lk_build_pyramid(lk_context *ctx, lk_pyramid *pyr, const uint8_t *d_img, int32_t pitch, lk_stream stream)
+{
+    if (!ctx || !pyr || !d_img) return fail(LK_ERR_INVALID_ARG, "ctx, pyr or d_img is NULL");
+    if (pyr->ctx != ctx) return fail(LK_ERR_INVALID_ARG, "pyramid belongs to another context");
+    if (pitch < pyr->desc.lv[0].w) return fail(LK_ERR_INVALID_ARG, "pitch %d < width %d", pitch, pyr->desc.lv[0].w);
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pyr->desc.lv[0].img = d_img;
+    pyr->desc.lv[0].pitch = pitch;
+    std::vector<DownJob> down[LK_MAX_LEVELS];
+    std::vector<GradJob> grads;
+    pyramid_jobs(pyr, down, &grads);
+    {
+        hipError_t e = launch_write_desc(pyr->d_desc, pyr->desc, s);
+        if (e != hipSuccess) return hip_fail(e, "descriptor write launch");
+    }
+    for (int l = 1; l < pyr->desc.levels; ++l) {
+        hipError_t e = launch_downsample(down[l][0], s);
+        if (e != hipSuccess) return hip_fail(e, "pyramid kernel launch");
+    }
+    for (auto &g : grads) {
+        hipError_t e = launch_grad(g, s);
+        if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
+    }
+    pyr->built = true;
+    return LK_SUCCESS;
+}
+
+lk_result lk_build_pyramids(lk_context *ctx, lk_pyramid *const *h_pyrs, const uint8_t *const *h_imgs,
+                            const int32_t *h_pitches, int32_t n, lk_stream stream)
+{
+    if (!ctx) return fail(LK_ERR_INVALID_ARG, "ctx is NULL");
+    if (n < 0) return fail(LK_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return LK_SUCCESS;
+    if (!h_pyrs || !h_imgs || !h_pitches) return fail(LK_ERR_INVALID_ARG, "NULL array");
+    for (int i = 0; i < n; ++i) {
+        if (!h_pyrs[i] || !h_imgs[i]) return fail(LK_ERR_INVALID_ARG, "item %d: NULL pyramid or image", i);
+        if (h_pyrs[i]->ctx != ctx) return fail(LK_ERR_INVALID_ARG, "item %d: pyramid of another context", i);
+        if (h_pitches[i] < h_pyrs[i]->desc.lv[0].w) return fail(LK_ERR_INVALID_ARG, "item %d: pitch < width", i);
+    }
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+        h_pyrs[i]->desc.lv[0].img = h_imgs[i];
+        h_pyrs[i]->desc.lv[0].pitch = h_pitches[i];
+    }
+    return enqueue_build(ctx, h_pyrs, n, s);
+}
+
+lk_result lk_pyramid_read_level(lk_context *ctx, const lk_pyramid *pyr, int32_t level, float *d_dst, float *d_grad,
+                                lk_stream stream)
+{
+    if (!ctx || !pyr || !d_dst) return fail(LK_ERR_INVALID_ARG, "ctx, pyr or d_dst is NULL");
+    if (level < 1 || level >= pyr->desc.levels) return fail(LK_ERR_INVALID_ARG, "level must be in [1, levels)");
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = launch_read_level(pyr->desc.lv[level], pyr->desc.storage, d_dst, d_grad,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "read level launch");
+}
+
+lk_result lk_track(lk_context *ctx, const lk_pyramid *prev, const lk_pyramid *next, const float *d_pts,
+                   const float *d_guess, int32_t n, const lk_params *params, float *d_out_pts, uint8_t *d_status,
+                   float *d_residual, int32_t *d_iters, lk_stream stream)
+{
+    if (!ctx || !prev || !next) return fail(LK_ERR_INVALID_ARG, "ctx, prev or next is NULL");
+    lk_result r = check_pair(ctx, prev, next, -1);
+    if (r != LK_SUCCESS) return r;
+    r = check_params(params, std::min(prev->desc.levels, next->desc.levels));
+    if (r != LK_SUCCESS) return r;
+    if (n < 0) return fail(LK_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return LK_SUCCESS;
+    if (!d_pts || !d_out_pts || !d_status || !d_residual)
+        return fail(LK_ERR_INVALID_ARG, "NULL point or output array");
+    if (params->use_guess && !d_guess) return fail(LK_ERR_INVALID_ARG, "use_guess set but d_guess is NULL");
+    (void)hipSetDevice(ctx->device);
+    TrackArgs a = make_args(params, n, d_pts, d_guess, d_out_pts, d_status, d_residual, d_iters);
+    hipError_t e = launch_track(prev->d_desc, next->d_desc, prev->desc.storage, a, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "tracker launch");
+}
+
+lk_result lk_track_batched(lk_context *ctx, const lk_pair *h_pairs, int32_t n_pairs, const float *d_pts,
+                           const float *d_guess, const lk_params *params, float *d_out_pts, uint8_t *d_status,
+                           float *d_residual, int32_t *d_iters, lk_stream stream)
+{
+    if (!ctx) return fail(LK_ERR_INVALID_ARG, "ctx is NULL");
+    if (n_pairs < 0) return fail(LK_ERR_INVALID_ARG, "n_pairs < 0");
+    if (n_pairs == 0) return LK_SUCCESS;
+    if (!h_pairs) return fail(LK_ERR_INVALID_ARG, "h_pairs is NULL");
+    std::vector<BatchItem> items;
+    int storage = -1;
+    long long total = 0;
+    lk_result r = plan_batch(ctx, h_pairs, n_pairs, params, &items, &storage, &total);
+    if (r != LK_SUCCESS) return r;
+    if (total == 0) return LK_SUCCESS;
+    if (!d_pts || !d_out_pts || !d_status || !d_residual)
+        return fail(LK_ERR_INVALID_ARG, "NULL point or output array");
+    if (params->use_guess && !d_guess) return fail(LK_ERR_INVALID_ARG, "use_guess set but d_guess is NULL");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StagingRing::Slot *slot = nullptr;
+    const size_t bytes = items.size() * sizeof(BatchItem);
+    r = ctx->staging.acquire(bytes, &slot);
+    if (r != LK_SUCCESS) return r;
+    std::memcpy(slot->host, items.data(), bytes);
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch table)");
+    TrackArgs a = make_args(params, (int)total, d_pts, d_guess, d_out_pts, d_status, d_residual, d_iters);
+    e = launch_track_batched(static_cast<const BatchItem *>(slot->dev), (int)items.size(), (int)total, a, storage, s);
+    (void)hipEventRecord(slot->done, s);
+    return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "batched tracker launch");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- shared helpers
+
+namespace lkmi {
+
+lk_result check_pair(const lk_context *ctx, const lk_pyramid *prev, const lk_pyramid *next, int idx)
+{
+    char tag[32] = "";
+    if (idx >= 0) snprintf(tag, sizeof tag, "pair %d: ", idx);
+    if (!prev || !next) return fail(LK_ERR_INVALID_ARG, "%sNULL pyramid", tag);
+    if (prev->ctx != ctx || next->ctx != ctx) return fail(LK_ERR_INVALID_ARG, "%spyramid of another context", tag);
+    if (!prev->built || !next->built) return fail(LK_ERR_INVALID_ARG, "%spyramid was never built", tag);
+    if (prev->desc.lv[0].w != next->desc.lv[0].w || prev->desc.lv[0].h != next->desc.lv[0].h)
+        return fail(LK_ERR_INVALID_ARG, "%sframes differ in size", tag);
+    if (prev->desc.storage != next->desc.storage) return fail(LK_ERR_INVALID_ARG, "%sstorages differ", tag);
+    return LK_SUCCESS;
+}
+
+lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
+                     std::vector<BatchItem> *items, int *storage, long long *total)
+{
+    int min_levels = LK_MAX_LEVELS;
+    *storage = -1;
+    *total = 0;
+    items->clear();
+    items->reserve(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) {
+        const lk_pair &p = pairs[i];
+        lk_result r = check_pair(ctx, p.prev, p.next, i);
+        if (r != LK_SUCCESS) return r;
+        if (p.n < 0 || p.pt_offset < 0 || p.reserved != 0)
+            return fail(LK_ERR_INVALID_ARG, "pair %d: negative n or offset, or reserved != 0", i);
+        if (*storage >= 0 && p.prev->desc.storage != *storage)
+            return fail(LK_ERR_INVALID_ARG, "pair %d: all pairs of one batch must share a storage", i);
+        *storage = p.prev->desc.storage;
+        min_levels = std::min(min_levels, std::min(p.prev->desc.levels, p.next->desc.levels));
+        BatchItem it;
+        it.prev = p.prev->d_desc;
+        it.next = p.next->d_desc;
+        it.pt_offset = p.pt_offset;
+        it.n = p.n;
+        it.first_wave = (int32_t)*total;
+        *total += p.n;
+        if (*total > (1LL << 30)) return fail(LK_ERR_INVALID_ARG, "more than 2^30 points in one batch");
+        items->push_back(it);
+    }
+    return check_params(params, min_levels);
+}
+
+lk_result enqueue_build(lk_context *ctx, lk_pyramid *const *pyrs, int n, hipStream_t s)
+{
+    std::vector<DownJob> down[LK_MAX_LEVELS];
+    std::vector<GradJob> grads;
+    for (int i = 0; i < n; ++i) pyramid_jobs(pyrs[i], down, &grads);
+    // one table: down jobs level by level, then gradient jobs
+    int tiles_down[LK_MAX_LEVELS] = {0};
+    size_t count = 0;
+    for (int l = 1; l < LK_MAX_LEVELS; ++l) {
+        int t = 0;
+        for (auto &j : down[l]) { j.tile_begin = t; t += j.tiles_x * ((j.dh + kDownTileH - 1) / kDownTileH); }
+        tiles_down[l] = t;
+        count += down[l].size();
+    }
+    int tiles_grad = 0;
+    for (auto &g : grads) { g.tile_begin = tiles_grad; tiles_grad += g.tiles_x * ((g.h + kGradTileH - 1) / kGradTileH); }
+    std::vector<PyrDescWrite> descs(n);
+    for (int i = 0; i < n; ++i) { descs[i].dst = pyrs[i]->d_desc; descs[i].desc = pyrs[i]->desc; }
+    const size_t bytes = count * sizeof(DownJob) + grads.size() * sizeof(GradJob) + descs.size() * sizeof(PyrDescWrite);
+    StagingRing::Slot *slot = nullptr;
+    lk_result r = ctx->staging.acquire(bytes, &slot);
+    if (r != LK_SUCCESS) return r;
+    char *hp = static_cast<char *>(slot->host);
+    size_t off[LK_MAX_LEVELS] = {0}, o = 0;
+    for (int l = 1; l < LK_MAX_LEVELS; ++l) {
+        off[l] = o;
+        if (!down[l].empty()) std::memcpy(hp + o, down[l].data(), down[l].size() * sizeof(DownJob));
+        o += down[l].size() * sizeof(DownJob);
+    }
+    const size_t goff = o;
+    if (!grads.empty()) std::memcpy(hp + o, grads.data(), grads.size() * sizeof(GradJob));
+    o += grads.size() * sizeof(GradJob);
+    const size_t doff = o;
+    std::memcpy(hp + o, descs.data(), descs.size() * sizeof(PyrDescWrite));
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(pyramid table)");
+    char *dp = static_cast<char *>(slot->dev);
+    e = launch_write_descs(reinterpret_cast<const PyrDescWrite *>(dp + doff), n, s);
+    for (int l = 1; l < LK_MAX_LEVELS && e == hipSuccess; ++l)
+        if (!down[l].empty())
+            e = launch_downsample_batched(reinterpret_cast<const DownJob *>(dp + off[l]), (int)down[l].size(),
+                                          tiles_down[l], s);
+    if (e == hipSuccess && !grads.empty())
+        e = launch_grad_batched(reinterpret_cast<const GradJob *>(dp + goff), (int)grads.size(), tiles_grad, s);
+    (void)hipEventRecord(slot->done, s);
+    if (e != hipSuccess) return hip_fail(e, "batched pyramid launch");
+    for (int i = 0; i < n; ++i) pyrs[i]->built = true;
+    return LK_SUCCESS;
+}
+
+}  // namespace lkmi
+
+void lk_context::graphs_release() {}

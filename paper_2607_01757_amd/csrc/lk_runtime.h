@@ -1,0 +1,60 @@
+// Host-side objects of liblkmi (context, pyramid, staging ring) and the
+// helpers shared by the ABI, the batched path and the server.
+#pragma once
+
+#include <atomic>
+#include <cstddef>
+#include <vector>
+
+#include "lk_internal.h"
+
+// Pinned host + device buffer pairs used to ship small tables (batch items,
+// pyramid jobs) to the device with one asynchronous copy.  A slot is reused
+// only after the event recorded behind its last user has completed.
+namespace lkmi {
+struct StagingRing {
+    struct Slot {
+        void *host = nullptr;
+        void *dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t done = nullptr;
+    };
+    std::vector<Slot> slots;
+    int next = 0;
+    lk_result init(int nslots);
+    void release();
+    lk_result acquire(size_t bytes, Slot **out);
+};
+}  // namespace lkmi
+
+struct lk_context {
+    int device = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> in_use{0};
+    lkmi::StagingRing staging;
+    void graphs_release();
+};
+
+struct lk_pyramid {
+    lk_context *ctx = nullptr;
+    lkmi::PyrDesc desc{};
+    lkmi::PyrDesc *d_desc = nullptr;   // device copy of desc, rewritten by every build
+    void *base = nullptr;      // descriptor, levels >= 1 and gradient planes, one allocation
+    size_t bytes = 0;
+    bool built = false;
+};
+
+namespace lkmi {
+lk_result fail(lk_result code, const char *fmt, ...);
+lk_result hip_fail(hipError_t e, const char *what);
+void clear_error();
+int level_dims(int w, int h, int levels, int32_t *ws, int32_t *hs);
+lk_result check_params(const lk_params *p, int pyr_levels);
+lk_result check_pair(const lk_context *ctx, const lk_pyramid *prev, const lk_pyramid *next, int idx);
+TrackArgs make_args(const lk_params *p, int n, const float *pts, const float *guess, float *out, uint8_t *st,
+                    float *res, int32_t *iters);
+lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
+                     std::vector<BatchItem> *items, int *storage, long long *total);
+lk_result enqueue_build(lk_context *ctx, lk_pyramid *const *pyrs, int n, hipStream_t s);
+void pyramid_jobs(const lk_pyramid *p, std::vector<DownJob> *down_by_level, std::vector<GradJob> *grads);
+}  // namespace lkmi

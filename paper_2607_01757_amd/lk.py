@@ -1,0 +1,190 @@
+"""ctypes binding of liblkmi (include/lk.h) -- argument marshalling only.
+
+Every function named ``lk_*`` here calls the C entry point of the same name;
+device arrays are torch tensors on the GPU (their ``data_ptr()`` is passed),
+streams are torch streams (their ``cuda_stream`` handle is passed).  All
+arithmetic runs in the HIP kernels of liblkmi.so; if the library is missing,
+importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblkmi.so")
+
+LK_SUCCESS, LK_ERR_INVALID_ARG, LK_ERR_OUT_OF_MEMORY, LK_ERR_DEVICE = 0, 1, 2, 3
+LK_ERR_BUSY, LK_ERR_NOT_READY, LK_ERR_NOT_FOUND, LK_ERR_NOT_IMPLEMENTED = 4, 5, 6, 7
+LK_STORAGE_F32, LK_STORAGE_F16 = 0, 1
+LK_OK, LK_LOST_EIG, LK_LOST_OOB, LK_LOST_FB = 0, 1, 2, 3
+LK_MAX_LEVELS = 8
+
+# Every symbol include/lk.h declares (checked by the CPU tests).
+ABI_SYMBOLS = (
+    "lk_params_default", "lk_last_error", "lk_context_create", "lk_context_destroy",
+    "lk_context_bytes_in_use", "lk_pyramid_create", "lk_pyramid_destroy", "lk_pyramid_info",
+    "lk_build_pyramid", "lk_build_pyramids", "lk_pyramid_read_level", "lk_track", "lk_track_batched",
+)
+
+
+class lk_params(C.Structure):
+    _fields_ = [("win", C.c_int32), ("levels", C.c_int32), ("max_iters", C.c_int32),
+                ("use_guess", C.c_int32), ("eps", C.c_float), ("min_eig", C.c_float),
+                ("fb_thresh", C.c_float), ("reserved", C.c_int32)]
+
+
+class lk_pair(C.Structure):
+    _fields_ = [("prev", C.c_void_p), ("next", C.c_void_p), ("pt_offset", C.c_int64),
+                ("n", C.c_int32), ("reserved", C.c_int32)]
+
+
+class LKError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("lk error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblkmi.so is not built (run: python -m paper_2607_01757_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, u64 = C.c_void_p, C.c_int32, C.c_uint64
+    res = C.c_int
+    sig = {
+        "lk_params_default": (lk_params, []),
+        "lk_last_error": (C.c_char_p, []),
+        "lk_context_create": (res, [i32, u64, C.POINTER(vp)]),
+        "lk_context_destroy": (None, [vp]),
+        "lk_context_bytes_in_use": (u64, [vp]),
+        "lk_pyramid_create": (res, [vp, i32, i32, i32, i32, C.POINTER(vp)]),
+        "lk_pyramid_destroy": (res, [vp]),
+        "lk_pyramid_info": (res, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
+        "lk_build_pyramid": (res, [vp, vp, vp, i32, vp]),
+        "lk_build_pyramids": (res, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(i32), i32, vp]),
+        "lk_pyramid_read_level": (res, [vp, vp, i32, vp, vp, vp]),
+        "lk_track": (res, [vp, vp, vp, vp, vp, i32, C.POINTER(lk_params), vp, vp, vp, vp, vp]),
+        "lk_track_batched": (res, [vp, C.POINTER(lk_pair), i32, vp, vp, C.POINTER(lk_params), vp, vp, vp,
+                                   vp, vp]),
+    }
+    for name, (rt, at) in sig.items():
+        f = getattr(lib, name)
+        f.restype = rt
+        f.argtypes = at
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != LK_SUCCESS:
+        raise LKError(rc, lib.lk_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ---------------------------------------------------------------- C names
+
+def lk_params_default() -> lk_params:
+    return lib.lk_params_default()
+
+
+def lk_last_error() -> str:
+    return lib.lk_last_error().decode()
+
+
+def lk_context_create(device: int = 0, hbm_budget_bytes: int = 0):
+    h = C.c_void_p()
+    _check(lib.lk_context_create(device, hbm_budget_bytes, C.byref(h)))
+    return h
+
+
+def lk_context_destroy(ctx):
+    lib.lk_context_destroy(ctx)
+
+
+def lk_context_bytes_in_use(ctx) -> int:
+    return lib.lk_context_bytes_in_use(ctx)
+
+
+def lk_pyramid_create(ctx, w: int, h: int, levels: int, storage: int = LK_STORAGE_F32):
+    p = C.c_void_p()
+    _check(lib.lk_pyramid_create(ctx, w, h, levels, storage, C.byref(p)))
+    return p
+
+
+def lk_pyramid_destroy(pyr):
+    _check(lib.lk_pyramid_destroy(pyr))
+
+
+def lk_pyramid_info(pyr):
+    v = [C.c_int32() for _ in range(4)]
+    _check(lib.lk_pyramid_info(pyr, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def lk_build_pyramid(ctx, pyr, img, pitch: int | None = None, stream=None):
+    """img: 2-D uint8 CUDA tensor (rows may be padded: pass the row pitch)."""
+    if pitch is None:
+        pitch = img.stride(0)
+    _check(lib.lk_build_pyramid(ctx, pyr, _ptr(img), pitch, _stream(stream)))
+
+
+def lk_build_pyramids(ctx, pyrs, imgs, pitches=None, stream=None):
+    n = len(pyrs)
+    if pitches is None:
+        pitches = [im.stride(0) for im in imgs]
+    P = (C.c_void_p * n)(*[p.value if isinstance(p, C.c_void_p) else p for p in pyrs])
+    I = (C.c_void_p * n)(*[_ptr(im) for im in imgs])
+    S = (C.c_int32 * n)(*pitches)
+    _check(lib.lk_build_pyramids(ctx, P, I, S, n, _stream(stream)))
+
+
+def lk_pyramid_read_level(ctx, pyr, level: int, dst, grad=None, stream=None):
+    _check(lib.lk_pyramid_read_level(ctx, pyr, level, _ptr(dst), _ptr(grad), _stream(stream)))
+
+
+def lk_track(ctx, prev, next, pts, guess, n: int, params: lk_params, out_pts, status, residual,
+             iters=None, stream=None):
+    _check(lib.lk_track(ctx, prev, next, _ptr(pts), _ptr(guess), n, C.byref(params), _ptr(out_pts),
+                        _ptr(status), _ptr(residual), _ptr(iters), _stream(stream)))
+
+
+def lk_track_batched(ctx, pairs, pts, guess, params: lk_params, out_pts, status, residual, iters=None,
+                     stream=None):
+    """pairs: sequence of (prev, next, pt_offset, n)."""
+    arr = (lk_pair * len(pairs))()
+    for i, (a, b, off, n) in enumerate(pairs):
+        arr[i].prev = a.value if isinstance(a, C.c_void_p) else a
+        arr[i].next = b.value if isinstance(b, C.c_void_p) else b
+        arr[i].pt_offset = off
+        arr[i].n = n
+        arr[i].reserved = 0
+    _check(lib.lk_track_batched(ctx, arr, len(pairs), _ptr(pts), _ptr(guess), C.byref(params),
+                                _ptr(out_pts), _ptr(status), _ptr(residual), _ptr(iters), _stream(stream)))
+
+
+# ---------------------------------------------------------------- helpers
+
+def make_params(win=21, levels=3, max_iters=30, eps=0.01, min_eig=1e-6, fb_thresh=0.0,
+                use_guess=False) -> lk_params:
+    return lk_params(win, levels, max_iters, int(use_guess), eps, min_eig, fb_thresh, 0)
+
+
+def outputs(n: int, levels: int, device="cuda", with_iters=False):
+    """Output tensors (points, status, residual, iters) for n points."""
+    import torch
+    return (torch.empty((n, 2), dtype=torch.float32, device=device),
+            torch.empty((n,), dtype=torch.uint8, device=device),
+            torch.empty((n,), dtype=torch.float32, device=device),
+            torch.empty((n, 2, levels), dtype=torch.int32, device=device) if with_iters else None)

@@ -123,6 +123,7 @@ class StereoSequence:
     max_rot_deg: float = 3.0
     max_trans: float = 12.0
     gain_range: tuple = (0.9, 1.1)
+    gain_mode: str = "smooth"     # "smooth": slowly varying exposure; "iid": independent per frame
     _canvas: np.ndarray = field(init=False, repr=False)
 
     def __post_init__(self):
@@ -136,7 +137,18 @@ class StereoSequence:
         self._ty = _sinusoid_path(rng, 0.22 * self.height, self.max_trans * 0.9)
         self._p1 = _sinusoid_path(rng, 5e-6, 1e-6)
         self._p2 = _sinusoid_path(rng, 5e-6, 1e-6)
-        self._gains = rng.uniform(*self.gain_range, size=(self.n_frames, 2))
+        lo, hi = self.gain_range
+        if self.gain_mode == "iid":
+            self._gains = rng.uniform(lo, hi, size=(self.n_frames, 2))
+        else:
+            # exposure drifts smoothly inside [lo, hi] (at most ~1% per frame);
+            # the right camera follows the left one with a fixed offset
+            drift = _sinusoid_path(rng, 1.0, 0.06)
+            t = np.arange(self.n_frames)
+            s = np.array([drift(k) for k in t])
+            left = 0.5 * (lo + hi) + 0.5 * (hi - lo) * s
+            right = np.clip(left * rng.uniform(0.98, 1.02), lo, hi)
+            self._gains = np.stack([left, right], axis=1)
         self._centre = np.array([cw / 2.0, ch / 2.0])
 
     def homography(self, t: int, camera: int = 0) -> np.ndarray:

@@ -1,0 +1,259 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Pyramids: float32 levels 1-2 of an 8-bit frame are exact (dyadic values with
+at most 24 significant bits), deeper levels within float rounding; binary16
+levels and gradient planes equal the oracle's binary16 storage bit for bit.
+Tracker: the rule of ``parity.compare`` -- same status and iteration counts
+away from decision thresholds, end points within 1e-3 px, residuals within
+1e-3 gray.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import GpuTracker, compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2607_01757_amd import lk as _lk
+    return _lk
+
+
+@pytest.fixture(scope="module")
+def ctx(lk):
+    c = lk.lk_context_create(0, 0)
+    yield c
+    lk.lk_context_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def gt(lk, ctx):
+    return GpuTracker(lk, ctx)
+
+
+# ------------------------------------------------------------------ pyramid
+
+@pytest.mark.parametrize("shape", [(480, 752), (121, 97), (64, 64), (33, 57), (1080, 1920)])
+def test_pyramid_levels_f32(lk, ctx, gt, shape):
+    import torch
+    rng = np.random.default_rng(shape[0])
+    img = rng.integers(0, 256, size=shape).astype(np.uint8)
+    levels = 4 if min(shape) >= 32 else 3
+    p, t = gt.pyramid(img, levels, lk.LK_STORAGE_F32)
+    ref, _, _ = oracle.pyramid(img.astype(np.float64), levels)
+    for l in range(1, levels):
+        h, w = ref[l].shape
+        d = torch.empty((h, w), dtype=torch.float32, device="cuda")
+        lk.lk_pyramid_read_level(ctx, p, l, d)
+        got = d.cpu().numpy().astype(np.float64)
+        if l <= 2:
+            assert np.array_equal(got, ref[l]), "level %d not exact" % l
+        else:
+            assert np.abs(got - ref[l]).max() <= 1e-4
+    lk.lk_pyramid_destroy(p)
+
+
+@pytest.mark.parametrize("shape", [(480, 752), (61, 83)])
+def test_pyramid_levels_and_gradients_f16(lk, ctx, gt, shape):
+    import torch
+    rng = np.random.default_rng(7 + shape[1])
+    img = rng.integers(0, 256, size=shape).astype(np.uint8)
+    levels = 4
+    p, t = gt.pyramid(img, levels, lk.LK_STORAGE_F16)
+    ref, rgx, rgy = oracle.pyramid(img.astype(np.float64), levels, f16=True)
+    for l in range(1, levels):
+        h, w = ref[l].shape
+        d = torch.empty((h, w), dtype=torch.float32, device="cuda")
+        g = torch.empty((h, w, 2), dtype=torch.float32, device="cuda")
+        lk.lk_pyramid_read_level(ctx, p, l, d, g)
+        gg = g.cpu().numpy().astype(np.float64)
+        assert np.array_equal(d.cpu().numpy().astype(np.float64), ref[l])
+        assert np.array_equal(gg[..., 0], rgx[l]) and np.array_equal(gg[..., 1], rgy[l])
+    lk.lk_pyramid_destroy(p)
+
+
+def test_batched_pyramid_build_matches_single(lk, ctx, gt):
+    import torch
+    rng = np.random.default_rng(3)
+    shapes = [(480, 752), (120, 160), (601, 959), (37, 41)]
+    imgs = [torch.from_numpy(rng.integers(0, 256, size=s).astype(np.uint8)).cuda() for s in shapes]
+    for storage in (lk.LK_STORAGE_F32, lk.LK_STORAGE_F16):
+        single, batch = [], []
+        for im in imgs:
+            h, w = im.shape
+            a = lk.lk_pyramid_create(ctx, w, h, 3, storage)
+            b = lk.lk_pyramid_create(ctx, w, h, 3, storage)
+            lk.lk_build_pyramid(ctx, a, im)
+            single.append(a)
+            batch.append(b)
+        lk.lk_build_pyramids(ctx, batch, imgs)
+        for a, b, im in zip(single, batch, imgs):
+            h, w = im.shape
+            for l in (1, 2):
+                hl, wl = (h + 1) // 2, (w + 1) // 2
+                if l == 2:
+                    hl, wl = (hl + 1) // 2, (wl + 1) // 2
+                da = torch.empty((hl, wl), dtype=torch.float32, device="cuda")
+                db = torch.empty((hl, wl), dtype=torch.float32, device="cuda")
+                ga = torch.zeros((hl, wl, 2), dtype=torch.float32, device="cuda")
+                gb = torch.zeros((hl, wl, 2), dtype=torch.float32, device="cuda")
+                lk.lk_pyramid_read_level(ctx, a, l, da, ga)
+                lk.lk_pyramid_read_level(ctx, b, l, db, gb)
+                torch.cuda.synchronize()
+                assert torch.equal(da, db) and torch.equal(ga, gb)
+            lk.lk_pyramid_destroy(a)
+            lk.lk_pyramid_destroy(b)
+
+
+# ------------------------------------------------------------------ tracker
+
+@pytest.mark.parametrize("seed", range(6))
+def test_single_pair_workload_fp32(gt, seed):
+    """752x480 frame pair, 150 keypoints, 21x21, 3 levels, 30 iterations, eps 0.01."""
+    p = synth.pair(seed)
+    g = gt.track(p.prev, p.next, p.pts)
+    r = oracle.track(p.prev, p.next, p.pts, min_eig=1e-6)
+    rep = compare(*g, r)
+    print("seed", seed, rep)
+    assert rep.compared_ok >= 100
+
+
+@pytest.mark.parametrize("t", [5, 400])
+def test_stereo_sequence_fp32_with_fb(gt, t):
+    """Temporal (left t-1 -> t) and stereo (left -> right) passes with a 1 px
+    forward-backward check, 21x21, 4 levels."""
+    seq = synth.StereoSequence(11, n_frames=1000)
+    l0, l1, r1 = seq.frame(t - 1), seq.frame(t), seq.frame(t, 1)
+    pts = seq.points(t, 200)
+    for a, b in [(l0, l1), (l1, r1)]:
+        g = gt.track(a, b, pts, levels=4, fb_thresh=1.0)
+        r = oracle.track(a, b, pts, levels=4, fb_thresh=1.0, min_eig=1e-6)
+        rp = oracle.track(a, b, pts.astype(np.float64) + 1e-5, levels=4, fb_thresh=1.0, min_eig=1e-6)
+        rep = compare(*g, r, r_perturbed=rp)
+        print(t, rep)
+        assert rep.compared_ok >= 100
+
+
+def test_stereo_sequence_independent_gains_stress(gt):
+    """Per-frame gains drawn independently in [0.9, 1.1]: brightness jumps of
+    up to 20% between frames, many points never converge.  Parity holds on
+    every well-conditioned point."""
+    seq = synth.StereoSequence(11, n_frames=1000, gain_mode="iid")
+    a, b = seq.frame(4), seq.frame(5)
+    pts = seq.points(5, 200)
+    g = gt.track(a, b, pts, levels=4, fb_thresh=1.0)
+    r = oracle.track(a, b, pts, levels=4, fb_thresh=1.0, min_eig=1e-6)
+    rp = oracle.track(a, b, pts.astype(np.float64) + 1e-5, levels=4, fb_thresh=1.0, min_eig=1e-6)
+    print(compare(*g, r, r_perturbed=rp))
+
+
+def test_identical_frames_bitwise_zero_flow(gt):
+    img = synth.pair(9).prev
+    pts = synth.uniform_points(np.random.default_rng(2), 300, 752, 480)
+    out, st, res, it = gt.track(img, img, pts, fb_thresh=0.5)
+    ok = st == 0
+    assert ok.mean() > 0.95
+    assert np.array_equal(out[ok], pts[ok])
+    assert np.all(res[ok] == 0.0)
+    assert np.all(it[ok, 0, :] == 1) and np.all(it[ok, 1, :] == 1)
+
+
+def test_constant_frame_lost_eig(gt):
+    img = np.full((120, 160), 90, np.uint8)
+    pts = np.array([[50.0, 60.0], [80.5, 30.25]], np.float32)
+    out, st, res, it = gt.track(img, img, pts, min_eig=1e-9)
+    assert np.all(st == 1)
+
+
+@pytest.mark.parametrize("win", [3, 5, 7, 9, 15, 19, 21, 23, 27, 31, 33, 41, 63])
+def test_window_sizes(gt, win):
+    p = synth.pair(20 + win, 320, 240, 60, max_shift=3.0)
+    levels = 2 if win > 31 else 3
+    g = gt.track(p.prev, p.next, p.pts, win=win, levels=levels)
+    r = oracle.track(p.prev, p.next, p.pts, win=win, levels=levels, min_eig=1e-6)
+    rep = compare(*g, r)
+    print(win, rep)
+
+
+@pytest.mark.parametrize("levels", [1, 2, 5])
+def test_level_counts(gt, levels):
+    p = synth.pair(30 + levels, 320, 256, 80, max_shift=1.5 if levels == 1 else 8.0)
+    g = gt.track(p.prev, p.next, p.pts, levels=levels)
+    r = oracle.track(p.prev, p.next, p.pts, levels=levels, min_eig=1e-6)
+    print(levels, compare(*g, r))
+
+
+def test_tiny_frame_coarsest_level_4px(gt):
+    canvas = synth.quantize_u8(synth.texture_canvas(40, 40, 41))
+    prev, nxt = canvas[4:36, 4:36].copy(), canvas[3:35, 5:37].copy()     # 32x32, shifted by (-1, +1)
+    pts = np.random.default_rng(4).uniform(2, 29, (12, 2)).astype(np.float32)
+    g = gt.track(prev, nxt, pts, win=7, levels=4)
+    r = oracle.track(prev, nxt, pts, win=7, levels=4, min_eig=1e-6)
+    print(compare(*g, r))
+
+
+def test_border_and_invalid_points(gt):
+    p = synth.pair(5, 200, 160, 10, max_shift=8.0)
+    pts = np.array([[0, 0], [199, 159], [0, 80], [199, 3], [1.5, 158.9], [100, 0.25],
+                    [-0.01, 50], [200.0, 50], [np.nan, 10], [10, np.inf], [3, 3], [196.5, 2]], np.float32)
+    g = gt.track(p.prev, p.next, pts, levels=3, fb_thresh=1.0)
+    r = oracle.track(p.prev, p.next, pts, levels=3, min_eig=1e-6, fb_thresh=1.0)
+    rep = compare(*g, r)
+    assert list(g[1][6:10]) == [2, 2, 2, 2]
+    print(rep)
+
+
+def test_initial_guesses(gt):
+    p = synth.pair(8, 640, 480, 120, max_shift=8.0)
+    guess = (p.gt + np.random.default_rng(1).normal(0, 1.0, p.gt.shape)).astype(np.float32)
+    g = gt.track(p.prev, p.next, p.pts, guess, fb_thresh=1.0)
+    r = oracle.track(p.prev, p.next, p.pts, guess, min_eig=1e-6, fb_thresh=1.0)
+    print(compare(*g, r))
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 63, 257])
+def test_ragged_point_counts(gt, n):
+    p = synth.pair(12, 256, 192, max(n, 1))
+    pts = p.pts[:n]
+    g = gt.track(p.prev, p.next, pts)
+    if n == 0:
+        return
+    r = oracle.track(p.prev, p.next, pts, min_eig=1e-6)
+    compare(*g, r)
+
+
+def test_max_iterations_and_eps(gt):
+    p = synth.pair(13, 400, 300, 100)
+    for mi, eps in [(1, 0.01), (5, 1e-4), (100, 1e-5)]:
+        g = gt.track(p.prev, p.next, p.pts, max_iters=mi, eps=eps)
+        r = oracle.track(p.prev, p.next, p.pts, max_iters=mi, eps=eps, min_eig=1e-6)
+        rp = oracle.track(p.prev, p.next, p.pts.astype(np.float64) + 1e-5, max_iters=mi, eps=eps, min_eig=1e-6)
+        rep = compare(*g, r, eps=eps, max_iters=10 ** 6, r_perturbed=rp)
+        print(mi, eps, rep)
+        assert rep.compared_ok >= 50
+
+
+# ------------------------------------------------------------------ binary16 storage
+
+@pytest.mark.parametrize("t", [3, 250])
+def test_f16_storage_matches_f16_oracle(gt, t):
+    """31x31, 4 levels, stereo pass with FB: vs the oracle with the same
+    binary16 storage rounding (tight), and vs the unrounded FP64 oracle
+    (the precision cost of binary16 storage, bound 1e-2 px)."""
+    seq = synth.StereoSequence(5, n_frames=1000)
+    a, b = seq.frame(t - 1), seq.frame(t)
+    pts = seq.points(t, 200)
+    g = gt.track(a, b, pts, win=31, levels=4, fb_thresh=1.0, storage=1)
+    r16 = oracle.track(a, b, pts, win=31, levels=4, fb_thresh=1.0, min_eig=1e-6, f16=True)
+    print("f16 vs f16-oracle", compare(*g, r16))
+    r64 = oracle.track(a, b, pts, win=31, levels=4, fb_thresh=1.0, min_eig=1e-6)
+    both = (g[1] == 0) & (r64.status == 0)
+    err = np.abs(g[0][both] - r64.pts[both]).max(axis=1)
+    print("f16 vs fp64-oracle: max %.4g p99 %.4g" % (err.max(), np.percentile(err, 99)))
+    assert np.percentile(err, 99) <= 1e-2
