@@ -172,6 +172,115 @@ lk_result lk_track_batched(lk_context *ctx, const lk_pair *h_pairs, int32_t n_pa
                            const float *d_guess, const lk_params *params, float *d_out_pts,
                            uint8_t *d_status, float *d_residual, int32_t *d_iters, lk_stream stream);
 
+/* ---- prepared batched steps (hipGraph, persistent launch, autotuner) ------
+ * A prepared step rebuilds the pyramids of n_builds frames (one launch per
+ * level for all of them) and then tracks every pair of n_pairs in one
+ * tracker launch -- the steady state of many camera streams, where each
+ * stream's previous pyramid stays resident and only its new frame is built.
+ * All pointers and shapes are fixed at creation; the job tables live in
+ * device memory, so lk_batch_run enqueues no copies.  Results are
+ * bit-identical to lk_build_pyramid + lk_track of each pair.
+ *
+ * Execution shapes (lk_exec_config) change speed, never results:
+ *   persistent = 0: one wavefront per keypoint, hardware dispatch;
+ *   persistent = 1: a grid of blocks_per_cu workgroups per compute unit,
+ *     each wavefront taking keypoints from per-XCD work counters (and
+ *     stealing from other XCDs when its own range is done);
+ *   use_graph = 1: the whole step is recorded into a HIP graph at creation
+ *     (and after lk_batch_tune) and replayed by lk_batch_run.
+ * lk_batch_tune times every candidate shape on this batch (reps launches
+ * each, HIP events), keeps the fastest and returns it.  Creation and tuning
+ * synchronize the device; lk_batch_run does not. */
+typedef struct {
+    int32_t n_builds;
+    lk_pyramid *const *build_pyrs;     /* host array of n_builds pyramids to rebuild */
+    const uint8_t *const *build_imgs;  /* host array of their 8-bit frames (device pointers) */
+    const int32_t *build_pitches;      /* host array of row pitches in bytes */
+    int32_t n_pairs;
+    const lk_pair *pairs;              /* host array of n_pairs pairs */
+    const float *d_pts;
+    const float *d_guess;
+    lk_params params;
+    float *d_out_pts;
+    uint8_t *d_status;
+    float *d_residual;
+    int32_t *d_iters;                  /* nullable */
+} lk_batch_desc;
+
+typedef struct {
+    int32_t persistent;
+    int32_t blocks_per_cu;
+    int32_t use_graph;
+    int32_t reserved;                  /* must be 0 */
+} lk_exec_config;
+
+typedef struct lk_batch lk_batch;
+
+lk_result lk_batch_create(lk_context *ctx, const lk_batch_desc *desc, const lk_exec_config *cfg /* NULL: defaults */,
+                          lk_batch **out);
+lk_result lk_batch_run(lk_batch *b, lk_stream stream);
+lk_result lk_batch_tune(lk_batch *b, lk_stream stream, int32_t reps, lk_exec_config *best, float *best_ms);
+lk_result lk_batch_config(const lk_batch *b, lk_exec_config *cfg);
+lk_result lk_batch_destroy(lk_batch *b);   /* waits for the batch's work */
+
+/* ---- serving (continuous batching over many camera streams) --------------
+ * A server owns, per camera stream, device frame buffers and two resident
+ * pyramids (the previous frame's and the current one's) plus pinned host
+ * staging.  Clients submit frames with their keypoints; a scheduler thread
+ * forms a batch from whatever is ready whenever one of `inflight` device
+ * streams is free, so frames that arrive while others are on the GPU join
+ * the next launch and launches overlap on the device.  A camera stream has
+ * at most one frame in flight (its previous pyramid is the dependency);
+ * further frames wait in its FIFO.  The first frame of a stream only primes
+ * its pyramid (its result has n = 0).  Streams are admitted while their
+ * resident bytes fit the budget; otherwise lk_server_open_stream returns
+ * LK_ERR_BUSY.  Results are bit-identical to lk_track on the same frames.
+ * Entry points may be called from any thread. */
+typedef struct {
+    int32_t max_streams;          /* size of the stream table */
+    int32_t max_points;           /* keypoints per frame, at most */
+    int32_t levels;               /* pyramid levels kept per stream (>= params.levels) */
+    int32_t storage;              /* LK_STORAGE_F32 or LK_STORAGE_F16 */
+    lk_params params;             /* tracker parameters for every stream */
+    int32_t max_batch;            /* frames per launch, at most */
+    int32_t inflight;             /* launches (device streams) in flight, 1..8 */
+    int32_t queue_depth;          /* frames per stream staged on the host (>= 1) */
+    int32_t reserved;             /* must be 0 */
+    uint64_t hbm_budget_bytes;    /* resident bytes of all streams (0: no limit) */
+} lk_server_config;
+
+typedef struct {
+    uint64_t submit_ns;           /* host monotonic clock (CLOCK_MONOTONIC) */
+    uint64_t launch_ns;           /* its batch was enqueued */
+    uint64_t done_ns;             /* the scheduler saw the batch complete */
+} lk_timing;
+
+typedef struct {
+    uint64_t frames;              /* frames completed */
+    uint64_t batches;             /* launches completed */
+    uint64_t points;              /* keypoints tracked */
+    uint64_t resident_bytes;      /* device bytes held by open streams */
+    int32_t open_streams;
+    int32_t reserved;
+} lk_server_stats;
+
+lk_result lk_server_create(lk_context *ctx, const lk_server_config *cfg, lk_server **out);
+lk_result lk_server_open_stream(lk_server *srv, int32_t w, int32_t h, uint32_t *id);
+/* Copies the frame (h x pitch bytes, w used per row) and the points before
+ * returning.  LK_ERR_BUSY: the stream's staging is full; poll and retry. */
+lk_result lk_server_submit(lk_server *srv, uint32_t id, const uint8_t *h_frame, int32_t pitch, const float *h_pts,
+                           const float *h_guess, int32_t n, uint64_t *ticket);
+/* LK_SUCCESS: results copied out (n_out points) and the ticket retired;
+ * LK_ERR_NOT_READY: still queued or running; LK_ERR_NOT_FOUND: unknown or
+ * already retired ticket; LK_ERR_DEVICE: the batch failed. */
+lk_result lk_server_poll(lk_server *srv, uint64_t ticket, float *h_out_pts, uint8_t *h_status, float *h_residual,
+                         int32_t *n_out, lk_timing *timing);
+/* Waits for the stream's running frame, drops its queued frames (their
+ * tickets become unknown) and frees its resources. */
+lk_result lk_server_close_stream(lk_server *srv, uint32_t id);
+lk_result lk_server_get_stats(lk_server *srv, lk_server_stats *out);
+void lk_server_destroy(lk_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

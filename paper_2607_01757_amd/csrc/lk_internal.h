@@ -94,6 +94,10 @@ hipError_t launch_write_desc(PyrDesc *d_dst, const PyrDesc &src, hipStream_t str
 hipError_t launch_write_descs(const PyrDescWrite *d_w, int n, hipStream_t stream);
 hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total_points,
                                 const TrackArgs &a, int storage, hipStream_t stream);
+// Persistent tracker grid: blocks_per_cu workgroups per compute unit; 8
+// work counters at d_counters (zeroed by the launch itself).
+hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
+                                   int storage, int *d_counters, int blocks_per_cu, int num_cus, hipStream_t stream);
 hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream);
 
 }  // namespace lkmi

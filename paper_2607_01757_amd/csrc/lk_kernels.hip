@@ -82,42 +82,114 @@ __device__ __forceinline__ float ldpx(const void *p, int idx)
 
 constexpr int kInW = 2 * kDownTileW + 3;   // input tile columns incl. halo
 constexpr int kInH = 2 * kDownTileH + 3;
+constexpr int kBufWord3 = 0x00020000;      // buffer resource word 3, gfx9 family: raw 32-bit access
+
+// Interior tiles stage their input with 16-byte loads starting CHUNK pixels
+// before the tile so that every load is aligned; border tiles take the
+// reflect-101 path one pixel at a time.
+template <int SK> struct Chunk { static constexpr int PX = SK == K_U8 ? 16 : (SK == K_F16 ? 8 : 4); };
+template <int SK> struct InRow {
+    static constexpr int PX = Chunk<SK>::PX;
+    static constexpr int N = (PX + 2 * kDownTileW + 1 + PX - 1) / PX;   // chunks per input row
+    static constexpr int W = N * PX;                                     // staged columns
+};
+constexpr int kInWMax = InRow<K_U8>::W > kInW ? InRow<K_U8>::W : kInW;
 
 struct DownSmem {
-    float in[kInH][kInW + 1];
-    float h[kInH][kDownTileW + 1];
+    float in[kInH][kInWMax + 1];
+    float h[kInH][kDownTileW + 4];
 };
+
+template <int SK>
+__device__ __forceinline__ void unpack_chunk(uint4 v, float *dst)
+{
+    if constexpr (SK == K_U8) {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) dst[k] = (float)((w[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+    } else if constexpr (SK == K_F16) {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float2 f = __half22float2(__builtin_bit_cast(__half2, w[k]));
+            dst[2 * k] = f.x;
+            dst[2 * k + 1] = f.y;
+        }
+    } else {
+        dst[0] = __builtin_bit_cast(float, v.x); dst[1] = __builtin_bit_cast(float, v.y);
+        dst[2] = __builtin_bit_cast(float, v.z); dst[3] = __builtin_bit_cast(float, v.w);
+    }
+}
 
 template <int SK, bool F16>
 __device__ void downsample_tile(const DownJob &j, int tile, DownSmem &sm)
 {
-    auto &s_in = sm.in;
-    auto &s_h = sm.h;
+    constexpr int es = SK == K_U8 ? 1 : (SK == K_F16 ? 2 : 4);
     const int tx = tile % j.tiles_x, ty = tile / j.tiles_x;
     const int ox0 = tx * kDownTileW, oy0 = ty * kDownTileH;
     const int sx0 = 2 * ox0 - 2, sy0 = 2 * oy0 - 2;
-    for (int i = threadIdx.x; i < kInH * kInW; i += kThreads) {
-        const int r = i / kInW, c = i - r * kInW;
+    constexpr int PX = Chunk<SK>::PX;
+    // staged columns cover input x in [a0, a0 + InRow::W); a0 is 16-byte aligned
+    const int a0 = sx0 + 2 - PX;
+    const bool vec_ok = ((j.spitch * es) & 15) == 0 && (reinterpret_cast<uintptr_t>(j.src) & 15) == 0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(j.src), (short)0, j.spitch * j.sh * es, kBufWord3);
+    for (int i = threadIdx.x; i < kInH * InRow<SK>::N; i += kThreads) {
+        const int r = i / InRow<SK>::N, c = i - r * InRow<SK>::N;
         const int gy = reflect101(min(sy0 + r, j.sh + 1), j.sh);
-        const int gx = reflect101(min(sx0 + c, j.sw + 1), j.sw);
-        s_in[r][c] = ldpx<SK>(j.src, gy * j.spitch + gx);
+        const int x0 = a0 + c * PX;
+        float *dst = &sm.in[r][c * PX];
+        if (vec_ok && x0 >= 0 && x0 + PX <= j.sw) {
+            const uint4 v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (gy * j.spitch + x0) * es, 0, 0));
+            unpack_chunk<SK>(v, dst);
+        } else {
+            // chunk crosses a frame edge: reflect-101 per pixel (never more
+            // than one reflection: x stays within [-PX, sw + PX))
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int gx = reflect101(clampi(x0 + k, -2, j.sw + 1), j.sw);
+                dst[k] = ldpx<SK>(j.src, gy * j.spitch + gx);
+            }
+        }
     }
+    const int off = PX - 2;                          // staged column of input x = sx0
     __syncthreads();
     // horizontal [1 4 6 4 1] at even columns; exact for short dyadic values
     for (int i = threadIdx.x; i < kInH * kDownTileW; i += kThreads) {
         const int r = i / kDownTileW, c = i - r * kDownTileW;
-        const float *q = &s_in[r][2 * c];
-        s_h[r][c] = ((q[0] + q[4]) + 4.0f * (q[1] + q[3]) + 6.0f * q[2]) * 0.0625f;
+        const float *q = &sm.in[r][2 * c + off];
+        sm.h[r][c] = ((q[0] + q[4]) + 4.0f * (q[1] + q[3]) + 6.0f * q[2]) * 0.0625f;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kDownTileH * kDownTileW; i += kThreads) {
-        const int r = i / kDownTileW, c = i - r * kDownTileW;
+    // vertical: each thread makes 4 consecutive outputs of one row
+    {
+        const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            v[k] = ((sm.h[2 * r][c + k] + sm.h[2 * r + 4][c + k]) + 4.0f * (sm.h[2 * r + 1][c + k] + sm.h[2 * r + 3][c + k])
+                    + 6.0f * sm.h[2 * r + 2][c + k]) * 0.0625f;
         const int ox = ox0 + c, oy = oy0 + r;
-        if (ox < j.dw && oy < j.dh) {
-            const float v = ((s_h[2 * r][c] + s_h[2 * r + 4][c]) + 4.0f * (s_h[2 * r + 1][c] + s_h[2 * r + 3][c])
-                             + 6.0f * s_h[2 * r + 2][c]) * 0.0625f;
-            if constexpr (F16) static_cast<__half *>(j.dst)[oy * j.dpitch + ox] = __float2half_rn(v);
-            else static_cast<float *>(j.dst)[oy * j.dpitch + ox] = v;
+        if (oy < j.dh) {
+            if (ox + 3 < j.dw) {
+                if constexpr (F16) {
+                    const __half2 a = __floats2half2_rn(v[0], v[1]), b = __floats2half2_rn(v[2], v[3]);
+                    uint2 u;
+                    u.x = __builtin_bit_cast(uint32_t, a);
+                    u.y = __builtin_bit_cast(uint32_t, b);
+                    *reinterpret_cast<uint2 *>(static_cast<__half *>(j.dst) + oy * j.dpitch + ox) = u;
+                } else {
+                    *reinterpret_cast<float4 *>(static_cast<float *>(j.dst) + oy * j.dpitch + ox) =
+                        make_float4(v[0], v[1], v[2], v[3]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (ox + k < j.dw) {
+                        if constexpr (F16) static_cast<__half *>(j.dst)[oy * j.dpitch + ox + k] = __float2half_rn(v[k]);
+                        else static_cast<float *>(j.dst)[oy * j.dpitch + ox + k] = v[k];
+                    }
+            }
         }
     }
 }
@@ -209,26 +281,102 @@ __global__ __launch_bounds__(kThreads) void k_grad_batched(const GradJob *jobs, 
 
 // =================================================================== tracker
 
-// Where a lane sits in the window.  Inactive lanes mirror lane 0's geometry
-// (so every address they form is valid) and contribute nothing.
-struct LaneCfg {
-    int c0, r0;          // first window column / row of this lane
-    int ext_x, ext_y;    // columns / rows spanned by all lanes' pixels
-    bool active;
-    bool lane0;          // writes per-point diagnostics
+// Buffer resource of one pyramid level: 32-bit offsets, and every access
+// beyond the level's bytes returns zero instead of faulting.
+
+struct Plane {
+    __amdgpu_buffer_rsrc_t rs;
+    int pitch, w, h;
 };
 
-template <int CW, int R>
+// A pointer every lane holds the same copy of, moved to scalar registers.
+template <class T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+
+// Level descriptor read from memory, made provably wave-uniform (the
+// descriptor is the same for the whole wavefront), so that buffer resources
+// built from it live in scalar registers.
+__device__ __forceinline__ LevelDesc uniform_level(const LevelDesc &d)
+{
+    LevelDesc u;
+    u.img = uniform_ptr(d.img);
+    u.grad = uniform_ptr(d.grad);
+    u.pitch = uniform_i(d.pitch);
+    u.gpitch = uniform_i(d.gpitch);
+    u.w = uniform_i(d.w);
+    u.h = uniform_i(d.h);
+    return u;
+}
+
+template <int KIND>
+__device__ __forceinline__ Plane make_plane(const void *base, int pitch, int w, int h)
+{
+    constexpr int es = KIND == K_U8 ? 1 : (KIND == K_F16 ? 2 : 4);
+    Plane p;
+    p.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, pitch * h * es, kBufWord3);
+    p.pitch = pitch; p.w = w; p.h = h;
+    return p;
+}
+
+template <int KIND>
+__device__ __forceinline__ float bload(const Plane &p, int idx)
+{
+    if constexpr (KIND == K_U8) return (float)__builtin_amdgcn_raw_buffer_load_b8(p.rs, idx, 0, 0);
+    else if constexpr (KIND == K_F16)
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(p.rs, idx * 2, 0, 0)));
+    else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs, idx * 4, 0, 0));
+}
+
+__device__ __forceinline__ float2 bload_h2(const __amdgpu_buffer_rsrc_t &rs, int idx)
+{
+    return __half22float2(__builtin_bit_cast(__half2, __builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4, 0, 0)));
+}
+
+// LDS writes of a wavefront become visible to its other lanes.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane layout of the window: lane (cg, sg) owns CW columns x R rows of
+// window pixels starting at (c0, r0).  WMAX is the largest window of the
+// layout; it fixes the staged regions.
+template <int CW_, int R_, int WMAX_, int WPB_, int OCC_>
+struct Geo {
+    static constexpr int CW = CW_, R = R_, WMAX = WMAX_, WPB = WPB_;
+    static constexpr int OCC = OCC_;                           // wavefronts per SIMD the registers must allow
+    static constexpr int EXX = ((WMAX + CW - 1) / CW) * CW;   // window columns covered by lanes
+    static constexpr int EXY = ((WMAX + R - 1) / R) * R;
+    static constexpr int TW = EXX + 1, TH = EXY + 1;           // bilinear taps
+    static constexpr int SW = TW + 2, SH = TH + 2;             // taps plus the Scharr halo
+    static constexpr int LDS = 3 * TW * TH + SW * SH;          // tap planes + staged level, floats per wavefront
+};
+
+// Inactive lanes mirror lane 0's geometry (every address they form is
+// valid) and contribute nothing.
+struct LaneCfg {
+    int c0, r0;
+    bool active;
+    bool lane0;
+};
+
+template <class G>
 __device__ __forceinline__ LaneCfg lane_cfg(int win, int lane)
 {
-    const int ncg = (win + CW - 1) / CW, nsg = (win + R - 1) / R;
+    const int ncg = (win + G::CW - 1) / G::CW, nsg = (win + G::R - 1) / G::R;
     LaneCfg c;
     c.active = lane < ncg * nsg;
     const int cg = c.active ? lane % ncg : 0, sg = c.active ? lane / ncg : 0;
-    c.c0 = cg * CW;
-    c.r0 = sg * R;
-    c.ext_x = ncg * CW;
-    c.ext_y = nsg * R;
+    c.c0 = cg * G::CW;
+    c.r0 = sg * G::R;
     c.lane0 = lane == 0;
     return c;
 }
@@ -236,90 +384,6 @@ __device__ __forceinline__ LaneCfg lane_cfg(int win, int lane)
 __device__ __forceinline__ bool c_valid(const LaneCfg &c, int win, int i, int j)
 {
     return c.active && (c.r0 + i < win) && (c.c0 + j < win);
-}
-
-// Raw taps of the target level around integer base (bx, by) = this lane's
-// first tap; indices clamped to the level (bilinear taps replicate edges).
-template <int KIND, int CW, int R>
-__device__ __forceinline__ void load_taps(const LevelDesc &L, int bx, int by, float (&t)[R + 1][CW + 1])
-{
-    int xs[CW + 1];
-#pragma unroll
-    for (int j = 0; j <= CW; ++j) xs[j] = clampi(bx + j, 0, L.w - 1);
-#pragma unroll
-    for (int i = 0; i <= R; ++i) {
-        const int row = clampi(by + i, 0, L.h - 1) * L.pitch;
-#pragma unroll
-        for (int j = 0; j <= CW; ++j) t[i][j] = ldpx<KIND>(L.img, row + xs[j]);
-    }
-}
-
-template <int CW, int R>
-__device__ __forceinline__ void load_taps_any(const LevelDesc &L, int level, int storage, int bx, int by,
-                                              float (&t)[R + 1][CW + 1])
-{
-    if (level == 0) load_taps<K_U8, CW, R>(L, bx, by, t);
-    else if (storage == LK_STORAGE_F16) load_taps<K_F16, CW, R>(L, bx, by, t);
-    else load_taps<K_F32, CW, R>(L, bx, by, t);
-}
-
-// Template of this lane: T, Gx, Gy at its window pixels, bilinear with the
-// shared weights w from the taps at positions (tx0 + j, ty0 + i), i <= R,
-// j <= CW.  Taps are clamped to the level; the Scharr stencil of a tap is
-// reflected about the level edges (reflect-101).  Tap rows are produced one
-// at a time and folded into the pixel rows they feed, which keeps few
-// registers live.
-
-template <int KIND, int CW>
-__device__ __forceinline__ void tap_row_scharr(const LevelDesc &L, int tx0, int y, bool interior,
-                                               float (&v)[CW + 1], float (&gx)[CW + 1], float (&gy)[CW + 1])
-{
-    if (interior) {
-        float e0[CW + 3], e1[CW + 3], e2[CW + 3];
-        const int r0 = (y - 1) * L.pitch + tx0 - 1, r1 = r0 + L.pitch, r2 = r1 + L.pitch;
-#pragma unroll
-        for (int k = 0; k < CW + 3; ++k) {
-            e0[k] = ldpx<KIND>(L.img, r0 + k);
-            e1[k] = ldpx<KIND>(L.img, r1 + k);
-            e2[k] = ldpx<KIND>(L.img, r2 + k);
-        }
-#pragma unroll
-        for (int j = 0; j <= CW; ++j) {
-            v[j] = e1[j + 1];
-            gx[j] = (3.0f * (e0[j + 2] - e0[j]) + 10.0f * (e1[j + 2] - e1[j]) + 3.0f * (e2[j + 2] - e2[j])) * 0.03125f;
-            gy[j] = (3.0f * (e2[j] - e0[j]) + 10.0f * (e2[j + 1] - e0[j + 1]) + 3.0f * (e2[j + 2] - e0[j + 2])) * 0.03125f;
-        }
-    } else {
-        const int yc = clampi(y, 0, L.h - 1);
-        const int ym = reflect101(yc - 1, L.h) * L.pitch, yp = reflect101(yc + 1, L.h) * L.pitch;
-        const int yr = yc * L.pitch;
-#pragma unroll
-        for (int j = 0; j <= CW; ++j) {
-            const int x = clampi(tx0 + j, 0, L.w - 1);
-            const int xm = reflect101(x - 1, L.w), xp = reflect101(x + 1, L.w);
-            const float a00 = ldpx<KIND>(L.img, ym + xm), a01 = ldpx<KIND>(L.img, ym + x), a02 = ldpx<KIND>(L.img, ym + xp);
-            const float a10 = ldpx<KIND>(L.img, yr + xm), a11 = ldpx<KIND>(L.img, yr + x), a12 = ldpx<KIND>(L.img, yr + xp);
-            const float a20 = ldpx<KIND>(L.img, yp + xm), a21 = ldpx<KIND>(L.img, yp + x), a22 = ldpx<KIND>(L.img, yp + xp);
-            v[j] = a11;
-            gx[j] = (3.0f * (a02 - a00) + 10.0f * (a12 - a10) + 3.0f * (a22 - a20)) * 0.03125f;
-            gy[j] = (3.0f * (a20 - a00) + 10.0f * (a21 - a01) + 3.0f * (a22 - a02)) * 0.03125f;
-        }
-    }
-}
-
-template <int KIND, int CW>
-__device__ __forceinline__ void tap_row_planes(const LevelDesc &L, int tx0, int y, float (&v)[CW + 1],
-                                               float (&gx)[CW + 1], float (&gy)[CW + 1])
-{
-    const int yc = clampi(y, 0, L.h - 1);
-#pragma unroll
-    for (int j = 0; j <= CW; ++j) {
-        const int x = clampi(tx0 + j, 0, L.w - 1);
-        v[j] = ldpx<KIND>(L.img, yc * L.pitch + x);
-        const float2 g = __half22float2(L.grad[yc * L.gpitch + x]);
-        gx[j] = g.x;
-        gy[j] = g.y;
-    }
 }
 
 struct Weights {
@@ -344,32 +408,121 @@ __device__ __forceinline__ float bilerp(const Weights &w, float a, float b, floa
     return fmaf(w.w11, d, fmaf(w.w01, c, fmaf(w.w10, b, w.w00 * a)));
 }
 
-// PLANES: read stored gradient planes instead of computing Scharr.
-template <int KIND, bool PLANES, int CW, int R>
-__device__ __forceinline__ void build_template(const LevelDesc &L, int tx0, int ty0, bool interior, const Weights &w,
-                                               const LaneCfg &lc, int win, float (&T)[R][CW], float (&GX)[R][CW],
-                                               float (&GY)[R][CW])
+__device__ __forceinline__ float scharr_x(const float *e, int i, int sw)
 {
-    float pv[CW + 1], pgx[CW + 1], pgy[CW + 1];   // previous tap row
+    return (3.0f * (e[i - sw + 1] - e[i - sw - 1]) + 10.0f * (e[i + 1] - e[i - 1])
+            + 3.0f * (e[i + sw + 1] - e[i + sw - 1])) * 0.03125f;
+}
+
+__device__ __forceinline__ float scharr_y(const float *e, int i, int sw)
+{
+    return (3.0f * (e[i + sw - 1] - e[i - sw - 1]) + 10.0f * (e[i + sw] - e[i - sw])
+            + 3.0f * (e[i + sw + 1] - e[i - sw + 1])) * 0.03125f;
+}
+
+// Tap planes of the template at level l, in LDS: for every tap position
+// (tx_lo + 1 + tc, ty_lo + 1 + tr), tc < TW, tr < TH, the image value and
+// its Scharr gradients.  Positions outside the level hold values that are
+// never read: the lanes read their taps at positions clamped to the level
+// (bilinear taps replicate the edges), and the gradient at a clamped
+// position only uses the level with reflect-101 borders.
+//
+// Float levels: the level region with a one-pixel halo is staged first
+// (coalesced loads, reflect-101 applied to the addresses), then every tap
+// position's gradients are computed from it.  Binary16 levels: value and
+// stored gradients are read directly.
+template <class G, int KIND, bool PLANES>
+__device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty_lo, int lane, float *lds)
+{
+    float *TI = lds, *TX = TI + G::TW * G::TH, *TY = TX + G::TW * G::TH;
+    const Plane P = make_plane<KIND>(L.img, L.pitch, L.w, L.h);
+    if constexpr (!PLANES) {
+        float *E = TY + G::TW * G::TH;
 #pragma unroll
-    for (int i = 0; i <= R; ++i) {
-        float v[CW + 1], gx[CW + 1], gy[CW + 1];
-        if constexpr (PLANES) tap_row_planes<KIND, CW>(L, tx0, ty0 + i, v, gx, gy);
-        else tap_row_scharr<KIND, CW>(L, tx0, ty0 + i, interior, v, gx, gy);
-        if (i > 0) {
-#pragma unroll
-            for (int j = 0; j < CW; ++j) {
-                const bool ok = c_valid(lc, win, i - 1, j);
-                const float t = bilerp(w, pv[j], pv[j + 1], v[j], v[j + 1]);
-                const float u = bilerp(w, pgx[j], pgx[j + 1], gx[j], gx[j + 1]);
-                const float q = bilerp(w, pgy[j], pgy[j + 1], gy[j], gy[j + 1]);
-                T[i - 1][j] = ok ? t : 0.0f;
-                GX[i - 1][j] = ok ? u : 0.0f;
-                GY[i - 1][j] = ok ? q : 0.0f;
+        for (int k = 0; k < (G::SW * G::SH + kWave - 1) / kWave; ++k) {
+            const int idx = lane + k * kWave;
+            if (idx < G::SW * G::SH) {
+                const int r = idx / G::SW, c = idx - r * G::SW;
+                const int y = reflect101(clampi(ty_lo + r, -1, L.h), L.h);
+                const int x = reflect101(clampi(tx_lo + c, -1, L.w), L.w);
+                E[idx] = bload<KIND>(P, y * L.pitch + x);
             }
         }
+        wave_lds_sync();
 #pragma unroll
-        for (int j = 0; j <= CW; ++j) { pv[j] = v[j]; pgx[j] = gx[j]; pgy[j] = gy[j]; }
+        for (int k = 0; k < (G::TW * G::TH + kWave - 1) / kWave; ++k) {
+            const int idx = lane + k * kWave;
+            if (idx < G::TW * G::TH) {
+                const int tr = idx / G::TW, tc = idx - tr * G::TW;
+                const int e = (tr + 1) * G::SW + tc + 1;
+                TI[idx] = E[e];
+                TX[idx] = scharr_x(E, e, G::SW);
+                TY[idx] = scharr_y(E, e, G::SW);
+            }
+        }
+    } else {
+        const __amdgpu_buffer_rsrc_t grs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<__half2 *>(L.grad), (short)0, L.gpitch * L.h * 4, kBufWord3);
+#pragma unroll
+        for (int k = 0; k < (G::TW * G::TH + kWave - 1) / kWave; ++k) {
+            const int idx = lane + k * kWave;
+            if (idx < G::TW * G::TH) {
+                const int tr = idx / G::TW, tc = idx - tr * G::TW;
+                const int x = clampi(tx_lo + 1 + tc, 0, L.w - 1);
+                const int y = clampi(ty_lo + 1 + tr, 0, L.h - 1);
+                TI[idx] = bload<KIND>(P, y * L.pitch + x);
+                const float2 g = bload_h2(grs, y * L.gpitch + x);
+                TX[idx] = g.x;
+                TY[idx] = g.y;
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
+// Template T, Gx, Gy of this lane's pixels from the tap planes, reading
+// every tap at its position clamped to the level.  (cx0, cy0): level
+// position of tap plane entry (0, 0).
+template <class G>
+__device__ __forceinline__ void lane_template(const float *lds, const LaneCfg &lc, int win, const Weights &w,
+                                              int tx0, int ty0, int cx0, int cy0, int lw, int lh,
+                                              float (&T)[G::R][G::CW], float (&GX)[G::R][G::CW],
+                                              float (&GY)[G::R][G::CW])
+{
+    const float *TI = lds, *TX = TI + G::TW * G::TH, *TY = TX + G::TW * G::TH;
+    int cc[G::CW + 1], cr[G::R + 1];
+#pragma unroll
+    for (int j = 0; j <= G::CW; ++j) cc[j] = clampi(tx0 + j, 0, lw - 1) - cx0;
+#pragma unroll
+    for (int i = 0; i <= G::R; ++i) cr[i] = (clampi(ty0 + i, 0, lh - 1) - cy0) * G::TW;
+#pragma unroll
+    for (int i = 0; i < G::R; ++i)
+#pragma unroll
+        for (int j = 0; j < G::CW; ++j) {
+            const int t00 = cr[i] + cc[j], t10 = cr[i] + cc[j + 1], t01 = cr[i + 1] + cc[j], t11 = cr[i + 1] + cc[j + 1];
+            const bool ok = c_valid(lc, win, i, j);
+            const float v = bilerp(w, TI[t00], TI[t10], TI[t01], TI[t11]);
+            const float u = bilerp(w, TX[t00], TX[t10], TX[t01], TX[t11]);
+            const float q = bilerp(w, TY[t00], TY[t10], TY[t01], TY[t11]);
+            T[i][j] = ok ? v : 0.0f;
+            GX[i][j] = ok ? u : 0.0f;
+            GY[i][j] = ok ? q : 0.0f;
+        }
+}
+
+// Raw taps of the target level with this lane's first tap at (bx, by);
+// indices clamped to the level (bilinear taps replicate the edges).
+template <class G, int KIND>
+__device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, float (&t)[G::R + 1][G::CW + 1])
+{
+    int xs[G::CW + 1];
+#pragma unroll
+    for (int j = 0; j <= G::CW; ++j) xs[j] = clampi(bx + j, 0, P.w - 1);
+#pragma unroll
+    for (int i = 0; i <= G::R; ++i) {
+        const int row = clampi(by + i, 0, P.h - 1) * P.pitch;
+#pragma unroll
+        for (int j = 0; j <= G::CW; ++j) t[i][j] = bload<KIND>(P, row + xs[j]);
     }
 }
 
@@ -381,16 +534,18 @@ struct PassResult {
 };
 
 // One coarse-to-fine pass of pyramid I (template) into pyramid J (target).
-template <int ST, int CW, int R>
+template <int ST, class G>
 __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, float py, float gx, float gy,
-                               const TrackArgs &a, const LaneCfg &lc, int32_t *iters)
+                               const TrackArgs &a, const LaneCfg &lc, int lane, float *lds, int32_t *iters)
 {
+    constexpr int R = G::R, CW = G::CW;
     const int win = a.win, h = (win - 1) >> 1, L = a.levels;
     const float nw = (float)(win * win);
     PassResult pr;
     pr.status = LK_OK;
     pr.ox = px; pr.oy = py; pr.fx = 0.0f; pr.fy = 0.0f; pr.res = 0.0f;
-    if (!(px >= 0.0f && px <= (float)(I.lv[0].w - 1) && py >= 0.0f && py <= (float)(I.lv[0].h - 1))) {
+    const int w0 = uniform_i(I.lv[0].w), h0 = uniform_i(I.lv[0].h);
+    if (!(px >= 0.0f && px <= (float)(w0 - 1) && py >= 0.0f && py <= (float)(h0 - 1))) {
         pr.status = LK_LOST_OOB;
         return pr;
     }
@@ -400,52 +555,53 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
     float cfx = 0.0f, cfy = 0.0f;
     int cix = 0, ciy = 0;
     for (int l = L - 1; l >= 0; --l) {
-        const LevelDesc &LI = I.lv[l];
-        const LevelDesc &LJ = J.lv[l];
+        const LevelDesc LI = uniform_level(I.lv[l]);
+        const LevelDesc LJ = uniform_level(J.lv[l]);
         const float cxs = ldexpf(px, -l), cys = ldexpf(py, -l);   // exact scaling
         const float flx = floorf(cxs), fly = floorf(cys);
         cix = (int)flx; ciy = (int)fly;
         cfx = cxs - flx; cfy = cys - fly;                         // exact
         // ---- template T, Gx, Gy on the window around c = p / 2^l
         {
-            const int tx0 = cix - h + lc.c0, ty0 = ciy - h + lc.r0;
-            const Weights w = bilinear_weights(cfx, cfy);
-            const bool interior = (cix - h - 1 >= 0) && (cix - h + lc.ext_x + 1 <= LI.w - 1)
-                                  && (ciy - h - 1 >= 0) && (ciy - h + lc.ext_y + 1 <= LI.h - 1);
-            if constexpr (ST == LK_STORAGE_F16) {
-                if (l == 0) build_template<K_U8, true, CW, R>(LI, tx0, ty0, interior, w, lc, win, T, GX, GY);
-                else build_template<K_F16, true, CW, R>(LI, tx0, ty0, interior, w, lc, win, T, GX, GY);
-            } else {
-                if (l == 0) build_template<K_U8, false, CW, R>(LI, tx0, ty0, interior, w, lc, win, T, GX, GY);
-                else build_template<K_F32, false, CW, R>(LI, tx0, ty0, interior, w, lc, win, T, GX, GY);
-            }
+            const int tx_lo = cix - h - 1, ty_lo = ciy - h - 1;
+            if (l == 0) stage_taps<G, K_U8, ST == LK_STORAGE_F16>(LI, tx_lo, ty_lo, lane, lds);
+            else if constexpr (ST == LK_STORAGE_F16) stage_taps<G, K_F16, true>(LI, tx_lo, ty_lo, lane, lds);
+            else stage_taps<G, K_F32, false>(LI, tx_lo, ty_lo, lane, lds);
+            lane_template<G>(lds, lc, win, bilinear_weights(cfx, cfy), cix - h + lc.c0, ciy - h + lc.r0,
+                             cix - h, ciy - h, LI.w, LI.h, T, GX, GY);
         }
         float sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
 #pragma unroll
         for (int i = 0; i < R; ++i)
 #pragma unroll
             for (int j = 0; j < CW; ++j) {
-                sxx += GX[i][j] * GX[i][j];
-                sxy += GX[i][j] * GY[i][j];
-                syy += GY[i][j] * GY[i][j];
+                sxx = fmaf(GX[i][j], GX[i][j], sxx);
+                sxy = fmaf(GX[i][j], GY[i][j], sxy);
+                syy = fmaf(GY[i][j], GY[i][j], syy);
             }
         const float Gxx = uniform_f(wave_sum(sxx)), Gxy = uniform_f(wave_sum(sxy)), Gyy = uniform_f(wave_sum(syy));
-        // eigenvalue test in double from the float sums (no cancellation from squaring)
+        // Eigenvalue test: lambda_min = det / lambda_max, with the determinant
+        // formed exactly in double (products of floats are exact there) and
+        // lambda_max, which has no cancellation, in float.
+        const double ddet = (double)Gxx * (double)Gyy - (double)Gxy * (double)Gxy;
+        const float det = (float)ddet;
         {
-            const double dxx = Gxx, dxy = Gxy, dyy = Gyy;
-            const double lam = 0.5 * (dxx + dyy - sqrt((dxx - dyy) * (dxx - dyy) + 4.0 * dxy * dxy));
-            const double meig = lam / ((double)nw * 65025.0);
-            if (!(meig >= (double)a.min_eig)) {
+            const float lmax = 0.5f * ((Gxx + Gyy) + sqrtf((Gxx - Gyy) * (Gxx - Gyy) + 4.0f * Gxy * Gxy));
+            const float meig = det / lmax / (nw * 65025.0f);
+            if (!(meig >= a.min_eig)) {
                 pr.status = LK_LOST_EIG;
                 pr.ox = ldexpf((float)cix + (cfx + gx), l);
                 pr.oy = ldexpf((float)ciy + (cfy + gy), l);
                 return pr;
             }
         }
-        const float det = Gxx * Gyy - Gxy * Gxy;
+        const float rdet = 1.0f / det;
         const float lox = (float)(-h - cix), hix = (float)(LJ.w - 1 + h - cix);
         const float loy = (float)(-h - ciy), hiy = (float)(LJ.h - 1 + h - ciy);
         const float eps2 = a.eps * a.eps;
+        const Plane PJ = l == 0 ? make_plane<K_U8>(LJ.img, LJ.pitch, LJ.w, LJ.h)
+                                : (ST == LK_STORAGE_F16 ? make_plane<K_F16>(LJ.img, LJ.pitch, LJ.w, LJ.h)
+                                                        : make_plane<K_F32>(LJ.img, LJ.pitch, LJ.w, LJ.h));
         int jbx = INT_MIN, jby = INT_MIN;
         dx = 0.0f; dy = 0.0f;
         int k = 0;
@@ -462,7 +618,9 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             const float fux = floorf(ux), fuy = floorf(uy);
             const int bx = cix + (int)fux, by = ciy + (int)fuy;
             if (bx != jbx || by != jby) {
-                load_taps_any<CW, R>(LJ, l, ST, bx - h + lc.c0, by - h + lc.r0, jt);
+                if (l == 0) load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, jt);
+                else if constexpr (ST == LK_STORAGE_F16) load_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, jt);
+                else load_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, jt);
                 jbx = bx; jby = by;
             }
             const Weights w = bilinear_weights(ux - fux, uy - fuy);
@@ -471,14 +629,13 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             for (int i = 0; i < R; ++i)
 #pragma unroll
                 for (int j = 0; j < CW; ++j) {
-                    const float jv = bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
-                    const float e = T[i][j] - jv;
-                    bxs += e * GX[i][j];
-                    bys += e * GY[i][j];
+                    const float e = T[i][j] - bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
+                    bxs = fmaf(e, GX[i][j], bxs);
+                    bys = fmaf(e, GY[i][j], bys);
                 }
             const float bx_ = uniform_f(wave_sum(bxs)), by_ = uniform_f(wave_sum(bys));
-            const float ex = (Gyy * bx_ - Gxy * by_) / det;
-            const float ey = (Gxx * by_ - Gxy * bx_) / det;
+            const float ex = (Gyy * bx_ - Gxy * by_) * rdet;
+            const float ey = (Gxx * by_ - Gxy * bx_) * rdet;
             dx += ex;
             dy += ey;
             if (ex * ex + ey * ey < eps2) break;
@@ -496,12 +653,13 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
     pr.fx = ux - cfx;
     pr.fy = uy - cfy;
     {
-        const LevelDesc &LJ = J.lv[0];
+        const LevelDesc LJ = uniform_level(J.lv[0]);
+        const Plane PJ = make_plane<K_U8>(LJ.img, LJ.pitch, LJ.w, LJ.h);
         // the last update is not range-checked: keep the tap base finite and
         // near the frame before converting (taps are clamped anyway)
         const float fux = fminf(fmaxf(floorf(ux), (float)(-cix - h - 2)), (float)(LJ.w + h + 2 - cix));
         const float fuy = fminf(fmaxf(floorf(uy), (float)(-ciy - h - 2)), (float)(LJ.h + h + 2 - ciy));
-        load_taps<K_U8, CW, R>(LJ, cix + (int)fux - h + lc.c0, ciy + (int)fuy - h + lc.r0, jt);
+        load_taps<G, K_U8>(PJ, cix + (int)fux - h + lc.c0, ciy + (int)fuy - h + lc.r0, jt);
         const Weights w = bilinear_weights(ux - fux, uy - fuy);
         float acc = 0.0f;
 #pragma unroll
@@ -519,10 +677,11 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
     return pr;
 }
 
-template <int ST, int CW, int R>
-__device__ void track_point(const PyrDesc &prev, const PyrDesc &next, const TrackArgs &a, int idx, int lane)
+template <int ST, class G>
+__device__ void track_point(const PyrDesc &prev, const PyrDesc &next, const TrackArgs &a, int idx, int lane,
+                            float *lds)
 {
-    const LaneCfg lc = lane_cfg<CW, R>(a.win, lane);
+    const LaneCfg lc = lane_cfg<G>(a.win, lane);
     const int L = a.levels;
     const float px = uniform_f(a.pts[2 * idx]), py = uniform_f(a.pts[2 * idx + 1]);
     float gx = 0.0f, gy = 0.0f;
@@ -533,10 +692,10 @@ __device__ void track_point(const PyrDesc &prev, const PyrDesc &next, const Trac
     int32_t *itp = a.iters ? a.iters + (size_t)idx * 2 * L : nullptr;
     if (itp && lc.lane0)
         for (int l = 0; l < 2 * L; ++l) itp[l] = 0;
-    PassResult f = run_pass<ST, CW, R>(prev, next, px, py, gx, gy, a, lc, itp);
+    PassResult f = run_pass<ST, G>(prev, next, px, py, gx, gy, a, lc, lane, lds, itp);
     int status = f.status;
     if (status == LK_OK && a.fb_thresh > 0.0f) {
-        PassResult b = run_pass<ST, CW, R>(next, prev, f.ox, f.oy, 0.0f, 0.0f, a, lc, itp ? itp + L : nullptr);
+        PassResult b = run_pass<ST, G>(next, prev, f.ox, f.oy, 0.0f, 0.0f, a, lc, lane, lds, itp ? itp + L : nullptr);
         if (b.status != LK_OK) {
             status = LK_LOST_FB;
         } else {
@@ -553,18 +712,33 @@ __device__ void track_point(const PyrDesc &prev, const PyrDesc &next, const Trac
     }
 }
 
-template <int ST, int CW, int R>
-__global__ __launch_bounds__(kThreads) void k_track(const PyrDesc *prev, const PyrDesc *next, TrackArgs a)
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
+// XCD works on one contiguous range of points (and of frames), which keeps
+// the pyramids it reads in its own L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
 {
-    const int wave = uniform_i((int)((blockIdx.x * kThreads + threadIdx.x) / kWave));
-    if (wave >= a.n) return;
-    track_point<ST, CW, R>(*prev, *next, a, wave, threadIdx.x & (kWave - 1));
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-template <int ST, int CW, int R>
-__global__ __launch_bounds__(kThreads) void k_track_batched(const BatchItem *items, int n_items, TrackArgs a)
+template <int ST, class G>
+__global__ __launch_bounds__(G::WPB * 64) __attribute__((amdgpu_waves_per_eu(G::OCC)))
+void k_track(const PyrDesc *prev, const PyrDesc *next, TrackArgs a)
 {
-    const int wave = uniform_i((int)((blockIdx.x * kThreads + threadIdx.x) / kWave));
+    __shared__ float s_lds[G::WPB * G::LDS];
+    const int wib = threadIdx.x >> 6;
+    const int wave = uniform_i(xcd_block(blockIdx.x, gridDim.x) * G::WPB + wib);
+    if (wave >= a.n) return;
+    track_point<ST, G>(*prev, *next, a, wave, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
+}
+
+template <int ST, class G>
+__global__ __launch_bounds__(G::WPB * 64) __attribute__((amdgpu_waves_per_eu(G::OCC)))
+void k_track_batched(const BatchItem *items, int n_items, TrackArgs a)
+{
+    __shared__ float s_lds[G::WPB * G::LDS];
+    const int wib = threadIdx.x >> 6;
+    const int wave = uniform_i(xcd_block(blockIdx.x, gridDim.x) * G::WPB + wib);
     if (wave >= a.n) return;
     int lo = 0, hi = n_items - 1;
     while (lo < hi) {
@@ -574,8 +748,52 @@ __global__ __launch_bounds__(kThreads) void k_track_batched(const BatchItem *ite
     lo = uniform_i(lo);
     const BatchItem &it = items[lo];
     const int idx = (int)(it.pt_offset + (wave - it.first_wave));
-    track_point<ST, CW, R>(*it.prev, *it.next, a, idx, threadIdx.x & (kWave - 1));
+    track_point<ST, G>(*it.prev, *it.next, a, idx, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
 }
+
+// Persistent form: a fixed grid whose wavefronts take keypoints from work
+// counters, one per XCD (XCD x first drains keypoints [x n/8, (x+1) n/8),
+// then helps the others).  Every wavefront leaves after one failed fetch per
+// counter, so the grid always drains.  The counters are zeroed by
+// k_reset_counters before each launch.
+template <int ST, class G>
+__global__ __launch_bounds__(G::WPB * 64) __attribute__((amdgpu_waves_per_eu(G::OCC)))
+void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *counters)
+{
+    __shared__ float s_lds[G::WPB * G::LDS];
+    const int wib = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const int xcd = blockIdx.x & 7;
+    for (int probe = 0; probe < 8; ++probe) {
+        const int owner = (xcd + probe) & 7;
+        const int first = (int)((long)a.n * owner / 8), end = (int)((long)a.n * (owner + 1) / 8);
+        for (;;) {
+            int w = 0;
+            if (lane == 0) w = atomicAdd(&counters[owner], 1);
+            const int wave = first + __builtin_amdgcn_readlane(w, 0);
+            if (wave >= end) break;
+            int lo = 0, hi = n_items - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (items[mid].first_wave <= wave) lo = mid; else hi = mid - 1;
+            }
+            lo = uniform_i(lo);
+            const BatchItem &it = items[lo];
+            const int idx = (int)(it.pt_offset + (wave - it.first_wave));
+            track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
+        }
+    }
+}
+
+__global__ void k_reset_counters(int *c)
+{
+    if (threadIdx.x < 8) c[threadIdx.x] = 0;
+}
+
+// Layouts: (CW, R) = (1, 7) for windows up to 21, (1, 16) up to 31,
+// (4, 16) up to 63; each keeps ceil(win/CW) * ceil(win/R) <= 64 lanes.
+using GeoW21 = Geo<1, 7, 21, 4, 4>;
+using GeoW31 = Geo<1, 16, 31, 4, 2>;
+using GeoW63 = Geo<4, 16, 63, 1, 1>;
 
 // Copies pyramid descriptors into device memory, in stream order.
 __global__ void k_write_desc(PyrDesc *dst, PyrDesc src) { if (threadIdx.x == 0) *dst = src; }
@@ -600,30 +818,41 @@ __global__ __launch_bounds__(kThreads) void k_read_level(LevelDesc lv, int stora
     }
 }
 
-inline unsigned blocks_for(long waves) { return (unsigned)((waves * kWave + kThreads - 1) / kThreads); }
+template <class G>
+inline unsigned blocks_for(long waves) { return (unsigned)((waves + G::WPB - 1) / G::WPB); }
+
+template <int ST, class G>
+hipError_t launch_track_g(const PyrDesc *prev, const PyrDesc *next, const TrackArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_track<ST, G>), dim3(blocks_for<G>(a.n)), dim3(G::WPB * 64), 0, s, prev, next, a);
+    return hipGetLastError();
+}
 
 template <int ST>
 hipError_t launch_track_st(const PyrDesc *prev, const PyrDesc *next, const TrackArgs &a, hipStream_t s)
 {
-    const unsigned grid = blocks_for(a.n);
     switch (choose_layout(a.win)) {
-    case LAYOUT_W21: hipLaunchKernelGGL((k_track<ST, 1, 7>), dim3(grid), dim3(kThreads), 0, s, prev, next, a); break;
-    case LAYOUT_W31: hipLaunchKernelGGL((k_track<ST, 1, 16>), dim3(grid), dim3(kThreads), 0, s, prev, next, a); break;
-    default: hipLaunchKernelGGL((k_track<ST, 4, 16>), dim3(grid), dim3(kThreads), 0, s, prev, next, a); break;
+    case LAYOUT_W21: return launch_track_g<ST, GeoW21>(prev, next, a, s);
+    case LAYOUT_W31: return launch_track_g<ST, GeoW31>(prev, next, a, s);
+    default: return launch_track_g<ST, GeoW63>(prev, next, a, s);
     }
+}
+
+template <int ST, class G>
+hipError_t launch_track_batched_g(const BatchItem *items, int n_items, const TrackArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_track_batched<ST, G>), dim3(blocks_for<G>(a.n)), dim3(G::WPB * 64), 0, s, items, n_items, a);
     return hipGetLastError();
 }
 
 template <int ST>
 hipError_t launch_track_batched_st(const BatchItem *items, int n_items, const TrackArgs &a, hipStream_t s)
 {
-    const unsigned grid = blocks_for(a.n);
     switch (choose_layout(a.win)) {
-    case LAYOUT_W21: hipLaunchKernelGGL((k_track_batched<ST, 1, 7>), dim3(grid), dim3(kThreads), 0, s, items, n_items, a); break;
-    case LAYOUT_W31: hipLaunchKernelGGL((k_track_batched<ST, 1, 16>), dim3(grid), dim3(kThreads), 0, s, items, n_items, a); break;
-    default: hipLaunchKernelGGL((k_track_batched<ST, 4, 16>), dim3(grid), dim3(kThreads), 0, s, items, n_items, a); break;
+    case LAYOUT_W21: return launch_track_batched_g<ST, GeoW21>(items, n_items, a, s);
+    case LAYOUT_W31: return launch_track_batched_g<ST, GeoW31>(items, n_items, a, s);
+    default: return launch_track_batched_g<ST, GeoW63>(items, n_items, a, s);
     }
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -684,6 +913,42 @@ hipError_t launch_write_descs(const PyrDescWrite *d_w, int n, hipStream_t stream
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_write_descs, dim3((n + 63) / 64), dim3(64), 0, stream, d_w, n);
     return hipGetLastError();
+}
+
+template <int ST, class G>
+hipError_t launch_track_persist_g(const BatchItem *items, int n_items, const TrackArgs &a, int *counters,
+                                  int grid, hipStream_t s)
+{
+    const int need = (a.n + G::WPB - 1) / G::WPB;
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);
+    hipLaunchKernelGGL((k_track_persist<ST, G>), dim3(grid < need ? grid : need), dim3(G::WPB * 64), 0, s, items,
+                       n_items, a, counters);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t launch_track_persist_st(const BatchItem *items, int n_items, const TrackArgs &a, int *counters,
+                                   int blocks_per_cu, int num_cus, hipStream_t s)
+{
+    switch (choose_layout(a.win)) {
+    case LAYOUT_W21:
+        return launch_track_persist_g<ST, GeoW21>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
+    case LAYOUT_W31:
+        return launch_track_persist_g<ST, GeoW31>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
+    default:
+        return launch_track_persist_g<ST, GeoW63>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
+    }
+}
+
+hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
+                                   int storage, int *d_counters, int blocks_per_cu, int num_cus, hipStream_t stream)
+{
+    if (total_points <= 0) return hipSuccess;
+    TrackArgs b = a;
+    b.n = total_points;
+    return storage == LK_STORAGE_F16
+               ? launch_track_persist_st<LK_STORAGE_F16>(d_items, n_items, b, d_counters, blocks_per_cu, num_cus, stream)
+               : launch_track_persist_st<LK_STORAGE_F32>(d_items, n_items, b, d_counters, blocks_per_cu, num_cus, stream);
 }
 
 hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,

@@ -445,50 +445,61 @@ lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const l
     return check_params(params, min_levels);
 }
 
+void make_build_tables(lk_pyramid *const *pyrs, int n, BuildTables *t)
+{
+    *t = BuildTables{};
+    t->descs.resize(n);
+    for (int i = 0; i < n; ++i) {
+        t->descs[i].dst = pyrs[i]->d_desc;
+        t->descs[i].desc = pyrs[i]->desc;
+        pyramid_jobs(pyrs[i], t->down, &t->grads);
+    }
+    size_t o = t->descs.size() * sizeof(PyrDescWrite);
+    for (int l = 1; l < LK_MAX_LEVELS; ++l) {
+        int tiles = 0;
+        for (auto &j : t->down[l]) { j.tile_begin = tiles; tiles += j.tiles_x * ((j.dh + kDownTileH - 1) / kDownTileH); }
+        t->tiles_down[l] = tiles;
+        t->off_down[l] = o;
+        o += t->down[l].size() * sizeof(DownJob);
+    }
+    for (auto &g : t->grads) { g.tile_begin = t->tiles_grad; t->tiles_grad += g.tiles_x * ((g.h + kGradTileH - 1) / kGradTileH); }
+    t->off_grad = o;
+    o += t->grads.size() * sizeof(GradJob);
+    t->bytes = o;
+}
+
+void BuildTables::pack(char *host) const
+{
+    std::memcpy(host, descs.data(), descs.size() * sizeof(PyrDescWrite));
+    for (int l = 1; l < LK_MAX_LEVELS; ++l)
+        if (!down[l].empty()) std::memcpy(host + off_down[l], down[l].data(), down[l].size() * sizeof(DownJob));
+    if (!grads.empty()) std::memcpy(host + off_grad, grads.data(), grads.size() * sizeof(GradJob));
+}
+
+hipError_t launch_build_tables(const BuildTables &t, const char *d_base, hipStream_t s)
+{
+    hipError_t e = launch_write_descs(reinterpret_cast<const PyrDescWrite *>(d_base), (int)t.descs.size(), s);
+    for (int l = 1; l < LK_MAX_LEVELS && e == hipSuccess; ++l)
+        if (!t.down[l].empty())
+            e = launch_downsample_batched(reinterpret_cast<const DownJob *>(d_base + t.off_down[l]),
+                                          (int)t.down[l].size(), t.tiles_down[l], s);
+    if (e == hipSuccess && !t.grads.empty())
+        e = launch_grad_batched(reinterpret_cast<const GradJob *>(d_base + t.off_grad), (int)t.grads.size(),
+                                t.tiles_grad, s);
+    return e;
+}
+
 lk_result enqueue_build(lk_context *ctx, lk_pyramid *const *pyrs, int n, hipStream_t s)
 {
-    std::vector<DownJob> down[LK_MAX_LEVELS];
-    std::vector<GradJob> grads;
-    for (int i = 0; i < n; ++i) pyramid_jobs(pyrs[i], down, &grads);
-    // one table: down jobs level by level, then gradient jobs
-    int tiles_down[LK_MAX_LEVELS] = {0};
-    size_t count = 0;
-    for (int l = 1; l < LK_MAX_LEVELS; ++l) {
-        int t = 0;
-        for (auto &j : down[l]) { j.tile_begin = t; t += j.tiles_x * ((j.dh + kDownTileH - 1) / kDownTileH); }
-        tiles_down[l] = t;
-        count += down[l].size();
-    }
-    int tiles_grad = 0;
-    for (auto &g : grads) { g.tile_begin = tiles_grad; tiles_grad += g.tiles_x * ((g.h + kGradTileH - 1) / kGradTileH); }
-    std::vector<PyrDescWrite> descs(n);
-    for (int i = 0; i < n; ++i) { descs[i].dst = pyrs[i]->d_desc; descs[i].desc = pyrs[i]->desc; }
-    const size_t bytes = count * sizeof(DownJob) + grads.size() * sizeof(GradJob) + descs.size() * sizeof(PyrDescWrite);
+    BuildTables t;
+    make_build_tables(pyrs, n, &t);
     StagingRing::Slot *slot = nullptr;
-    lk_result r = ctx->staging.acquire(bytes, &slot);
+    lk_result r = ctx->staging.acquire(t.bytes, &slot);
     if (r != LK_SUCCESS) return r;
-    char *hp = static_cast<char *>(slot->host);
-    size_t off[LK_MAX_LEVELS] = {0}, o = 0;
-    for (int l = 1; l < LK_MAX_LEVELS; ++l) {
-        off[l] = o;
-        if (!down[l].empty()) std::memcpy(hp + o, down[l].data(), down[l].size() * sizeof(DownJob));
-        o += down[l].size() * sizeof(DownJob);
-    }
-    const size_t goff = o;
-    if (!grads.empty()) std::memcpy(hp + o, grads.data(), grads.size() * sizeof(GradJob));
-    o += grads.size() * sizeof(GradJob);
-    const size_t doff = o;
-    std::memcpy(hp + o, descs.data(), descs.size() * sizeof(PyrDescWrite));
-    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
+    t.pack(static_cast<char *>(slot->host));
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, t.bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(pyramid table)");
-    char *dp = static_cast<char *>(slot->dev);
-    e = launch_write_descs(reinterpret_cast<const PyrDescWrite *>(dp + doff), n, s);
-    for (int l = 1; l < LK_MAX_LEVELS && e == hipSuccess; ++l)
-        if (!down[l].empty())
-            e = launch_downsample_batched(reinterpret_cast<const DownJob *>(dp + off[l]), (int)down[l].size(),
-                                          tiles_down[l], s);
-    if (e == hipSuccess && !grads.empty())
-        e = launch_grad_batched(reinterpret_cast<const GradJob *>(dp + goff), (int)grads.size(), tiles_grad, s);
+    e = launch_build_tables(t, static_cast<const char *>(slot->dev), s);
     (void)hipEventRecord(slot->done, s);
     if (e != hipSuccess) return hip_fail(e, "batched pyramid launch");
     for (int i = 0; i < n; ++i) pyrs[i]->built = true;

@@ -45,6 +45,22 @@ struct lk_pyramid {
 };
 
 namespace lkmi {
+
+// Job tables of a batched pyramid build, laid out for one device buffer:
+// descriptor writes, down jobs level by level, then gradient jobs.
+struct BuildTables {
+    std::vector<PyrDescWrite> descs;
+    std::vector<DownJob> down[LK_MAX_LEVELS];
+    std::vector<GradJob> grads;
+    int tiles_down[LK_MAX_LEVELS] = {0};
+    int tiles_grad = 0;
+    size_t off_down[LK_MAX_LEVELS] = {0}, off_grad = 0, bytes = 0;
+    void pack(char *host) const;
+};
+void make_build_tables(lk_pyramid *const *pyrs, int n, BuildTables *t);
+// Enqueues the build from tables already in device memory at d_base.
+hipError_t launch_build_tables(const BuildTables &t, const char *d_base, hipStream_t s);
+
 lk_result fail(lk_result code, const char *fmt, ...);
 lk_result hip_fail(hipError_t e, const char *what);
 void clear_error();

@@ -25,6 +25,9 @@ ABI_SYMBOLS = (
     "lk_params_default", "lk_last_error", "lk_context_create", "lk_context_destroy",
     "lk_context_bytes_in_use", "lk_pyramid_create", "lk_pyramid_destroy", "lk_pyramid_info",
     "lk_build_pyramid", "lk_build_pyramids", "lk_pyramid_read_level", "lk_track", "lk_track_batched",
+    "lk_batch_create", "lk_batch_run", "lk_batch_tune", "lk_batch_config", "lk_batch_destroy",
+    "lk_server_create", "lk_server_open_stream", "lk_server_submit", "lk_server_poll", "lk_server_close_stream",
+    "lk_server_get_stats", "lk_server_destroy",
 )
 
 
@@ -37,6 +40,35 @@ class lk_params(C.Structure):
 class lk_pair(C.Structure):
     _fields_ = [("prev", C.c_void_p), ("next", C.c_void_p), ("pt_offset", C.c_int64),
                 ("n", C.c_int32), ("reserved", C.c_int32)]
+
+
+class lk_batch_desc(C.Structure):
+    _fields_ = [("n_builds", C.c_int32), ("build_pyrs", C.POINTER(C.c_void_p)),
+                ("build_imgs", C.POINTER(C.c_void_p)), ("build_pitches", C.POINTER(C.c_int32)),
+                ("n_pairs", C.c_int32), ("pairs", C.POINTER(lk_pair)), ("d_pts", C.c_void_p),
+                ("d_guess", C.c_void_p), ("params", lk_params), ("d_out_pts", C.c_void_p),
+                ("d_status", C.c_void_p), ("d_residual", C.c_void_p), ("d_iters", C.c_void_p)]
+
+
+class lk_exec_config(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class lk_server_config(C.Structure):
+    _fields_ = [("max_streams", C.c_int32), ("max_points", C.c_int32), ("levels", C.c_int32),
+                ("storage", C.c_int32), ("params", lk_params), ("max_batch", C.c_int32),
+                ("inflight", C.c_int32), ("queue_depth", C.c_int32), ("reserved", C.c_int32),
+                ("hbm_budget_bytes", C.c_uint64)]
+
+
+class lk_timing(C.Structure):
+    _fields_ = [("submit_ns", C.c_uint64), ("launch_ns", C.c_uint64), ("done_ns", C.c_uint64)]
+
+
+class lk_server_stats(C.Structure):
+    _fields_ = [("frames", C.c_uint64), ("batches", C.c_uint64), ("points", C.c_uint64),
+                ("resident_bytes", C.c_uint64), ("open_streams", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LKError(RuntimeError):
@@ -66,6 +98,18 @@ def _load():
         "lk_track": (res, [vp, vp, vp, vp, vp, i32, C.POINTER(lk_params), vp, vp, vp, vp, vp]),
         "lk_track_batched": (res, [vp, C.POINTER(lk_pair), i32, vp, vp, C.POINTER(lk_params), vp, vp, vp,
                                    vp, vp]),
+        "lk_batch_create": (res, [vp, C.POINTER(lk_batch_desc), C.POINTER(lk_exec_config), C.POINTER(vp)]),
+        "lk_batch_run": (res, [vp, vp]),
+        "lk_batch_tune": (res, [vp, vp, i32, C.POINTER(lk_exec_config), C.POINTER(C.c_float)]),
+        "lk_batch_config": (res, [vp, C.POINTER(lk_exec_config)]),
+        "lk_batch_destroy": (res, [vp]),
+        "lk_server_create": (res, [vp, C.POINTER(lk_server_config), C.POINTER(vp)]),
+        "lk_server_open_stream": (res, [vp, i32, i32, C.POINTER(C.c_uint32)]),
+        "lk_server_submit": (res, [vp, C.c_uint32, vp, i32, vp, vp, i32, C.POINTER(C.c_uint64)]),
+        "lk_server_poll": (res, [vp, C.c_uint64, vp, vp, vp, C.POINTER(i32), C.POINTER(lk_timing)]),
+        "lk_server_close_stream": (res, [vp, C.c_uint32]),
+        "lk_server_get_stats": (res, [vp, C.POINTER(lk_server_stats)]),
+        "lk_server_destroy": (None, [vp]),
     }
     for name, (rt, at) in sig.items():
         f = getattr(lib, name)
@@ -174,7 +218,113 @@ def lk_track_batched(ctx, pairs, pts, guess, params: lk_params, out_pts, status,
                                 _ptr(out_pts), _ptr(status), _ptr(residual), _ptr(iters), _stream(stream)))
 
 
+def _hv(p):
+    return p.value if isinstance(p, C.c_void_p) else p
+
+
+def lk_batch_create(ctx, build_pyrs, build_imgs, pairs, pts, guess, params: lk_params, out_pts, status,
+                    residual, iters=None, config: lk_exec_config | None = None, build_pitches=None):
+    """build_pyrs / build_imgs: pyramids rebuilt each run and their uint8
+    CUDA frames; pairs: sequence of (prev, next, pt_offset, n)."""
+    nb = len(build_pyrs)
+    P = (C.c_void_p * max(nb, 1))(*[_hv(p) for p in build_pyrs])
+    I = (C.c_void_p * max(nb, 1))(*[_ptr(im) for im in build_imgs])
+    pitches = build_pitches if build_pitches is not None else [im.stride(0) for im in build_imgs]
+    S = (C.c_int32 * max(nb, 1))(*pitches)
+    arr = (lk_pair * max(len(pairs), 1))()
+    for i, (a, b, off, n) in enumerate(pairs):
+        arr[i].prev, arr[i].next, arr[i].pt_offset, arr[i].n, arr[i].reserved = _hv(a), _hv(b), off, n, 0
+    d = lk_batch_desc(nb, P, I, S, len(pairs), arr, _ptr(pts), _ptr(guess), params, _ptr(out_pts), _ptr(status),
+                      _ptr(residual), _ptr(iters))
+    h = C.c_void_p()
+    _check(lib.lk_batch_create(ctx, C.byref(d), C.byref(config) if config is not None else None, C.byref(h)))
+    return h
+
+
+def lk_batch_run(batch, stream=None):
+    _check(lib.lk_batch_run(batch, _stream(stream)))
+
+
+def lk_batch_tune(batch, reps: int = 5, stream=None):
+    cfg = lk_exec_config()
+    ms = C.c_float()
+    _check(lib.lk_batch_tune(batch, _stream(stream), reps, C.byref(cfg), C.byref(ms)))
+    return cfg, ms.value
+
+
+def lk_batch_config(batch) -> lk_exec_config:
+    cfg = lk_exec_config()
+    _check(lib.lk_batch_config(batch, C.byref(cfg)))
+    return cfg
+
+
+def lk_batch_destroy(batch):
+    _check(lib.lk_batch_destroy(batch))
+
+
+def lk_server_create(ctx, cfg: lk_server_config):
+    h = C.c_void_p()
+    _check(lib.lk_server_create(ctx, C.byref(cfg), C.byref(h)))
+    return h
+
+
+def lk_server_open_stream(srv, w: int, h: int) -> int:
+    sid = C.c_uint32()
+    _check(lib.lk_server_open_stream(srv, w, h, C.byref(sid)))
+    return sid.value
+
+
+def lk_server_submit(srv, sid: int, frame, pts, guess=None) -> int:
+    """frame: 2-D uint8 numpy array; pts/guess: float32 numpy arrays N x 2."""
+    import numpy as np
+    frame = np.ascontiguousarray(frame, dtype=np.uint8)
+    p = np.ascontiguousarray(pts, dtype=np.float32).reshape(-1, 2)
+    g = None if guess is None else np.ascontiguousarray(guess, dtype=np.float32).reshape(-1, 2)
+    t = C.c_uint64()
+    _check(lib.lk_server_submit(srv, sid, frame.ctypes.data, frame.shape[1], p.ctypes.data if len(p) else None,
+                                None if g is None else g.ctypes.data, len(p), C.byref(t)))
+    return t.value
+
+
+def lk_server_poll(srv, ticket: int, max_points: int):
+    """Returns None while not ready, else (pts, status, residual, timing)."""
+    import numpy as np
+    out = np.zeros((max_points, 2), np.float32)
+    st = np.zeros(max_points, np.uint8)
+    res = np.zeros(max_points, np.float32)
+    n = C.c_int32()
+    tm = lk_timing()
+    rc = lib.lk_server_poll(srv, ticket, out.ctypes.data, st.ctypes.data, res.ctypes.data, C.byref(n), C.byref(tm))
+    if rc == LK_ERR_NOT_READY:
+        return None
+    _check(rc)
+    k = n.value
+    return out[:k], st[:k], res[:k], (tm.submit_ns, tm.launch_ns, tm.done_ns)
+
+
+def lk_server_close_stream(srv, sid: int):
+    _check(lib.lk_server_close_stream(srv, sid))
+
+
+def lk_server_get_stats(srv) -> lk_server_stats:
+    st = lk_server_stats()
+    _check(lib.lk_server_get_stats(srv, C.byref(st)))
+    return st
+
+
+def lk_server_destroy(srv):
+    lib.lk_server_destroy(srv)
+
+
 # ---------------------------------------------------------------- helpers
+
+def server_config(max_streams=256, max_points=1500, levels=4, storage=LK_STORAGE_F16, params=None,
+                  max_batch=256, inflight=2, queue_depth=4, hbm_budget_bytes=64 << 30) -> lk_server_config:
+    prm = params if params is not None else make_params(31, levels, 30, 0.01, 1e-6, 1.0)
+    return lk_server_config(max_streams, max_points, levels, storage, prm, max_batch, inflight, queue_depth, 0,
+                            hbm_budget_bytes)
+
+
 
 def make_params(win=21, levels=3, max_iters=30, eps=0.01, min_eig=1e-6, fb_thresh=0.0,
                 use_guess=False) -> lk_params:

@@ -61,12 +61,15 @@ def unstable(r: oracle.Result, r_perturbed: oracle.Result, tol: float) -> np.nda
 
 def compare(pts, status, residual, iters, r: oracle.Result, *, band=1e-4, pos_tol=1e-3,
             res_abs=1e-3, res_rel=1e-4, check_iters=True, eps=0.01, max_iters=30,
-            r_perturbed: oracle.Result | None = None, loose_tol=None) -> Report:
+            r_perturbed: oracle.Result | None = None, loose_tol=None, conv_band=None) -> Report:
     pts = np.asarray(pts, dtype=np.float64)
     status = np.asarray(status)
     residual = np.asarray(residual, dtype=np.float64)
     n = len(status)
-    excl = near_threshold(r, band) | capped(r, max_iters)
+    m = r.margins
+    cb = band if conv_band is None else conv_band
+    excl = ((m[:, 0] <= band) | (m[:, 1] <= band) | (m[:, 2] <= cb) | (m[:, 3] <= band)
+            | capped(r, max_iters))
     if r_perturbed is not None:
         excl |= unstable(r, r_perturbed, pos_tol / 4)
     keep = ~excl
@@ -79,7 +82,8 @@ def compare(pts, status, residual, iters, r: oracle.Result, *, band=1e-4, pos_to
     if check_iters and iters is not None:
         it = np.asarray(iters)
         it_mm = int(np.sum(np.any(it != r.iters, axis=(1, 2)) & both))
-    loose = near_threshold(r, band) & ~capped(r, max_iters) & (status == 0) & (r.status == 0)
+    near = (m[:, 0] <= band) | (m[:, 1] <= band) | (m[:, 2] <= cb) | (m[:, 3] <= band)
+    loose = near & ~capped(r, max_iters) & (status == 0) & (r.status == 0)
     if r_perturbed is not None:
         loose &= ~unstable(r, r_perturbed, pos_tol / 4)
     rep = Report(n=n, excluded=int(excl.sum()), compared_ok=int(both.sum()),

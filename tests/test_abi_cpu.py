@@ -1,0 +1,63 @@
+"""The C ABI library loads on a machine without a GPU and exports every
+entry point include/lk.h declares; host-side argument checks reject bad
+calls before any device work (no compute call is made here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lk_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lk():
+    from paper_2607_01757_amd import lk as _lk
+    return _lk
+
+
+def test_every_declared_symbol_is_exported(lk):
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lk.lib, n), n
+    assert sorted(lk.ABI_SYMBOLS) == names
+
+
+def test_defaults(lk):
+    p = lk.lk_params_default()
+    assert (p.win, p.levels, p.max_iters, p.use_guess) == (21, 3, 30, 0)
+    assert abs(p.eps - 0.01) < 1e-9 and abs(p.min_eig - 1e-6) < 1e-12 and p.fb_thresh == 0.0
+
+
+def test_null_arguments_rejected_on_host(lk):
+    L = lk.lib
+    out = C.c_void_p()
+    assert L.lk_pyramid_create(None, 64, 64, 3, 0, C.byref(out)) == lk.LK_ERR_INVALID_ARG
+    assert "NULL" in lk.lk_last_error()
+    prm = lk.make_params()
+    assert L.lk_track(None, None, None, None, None, 0, C.byref(prm), None, None, None, None, None) \
+        == lk.LK_ERR_INVALID_ARG
+    assert L.lk_track_batched(None, None, 0, None, None, C.byref(prm), None, None, None, None, None) \
+        == lk.LK_ERR_INVALID_ARG
+    assert L.lk_batch_create(None, None, None, C.byref(out)) == lk.LK_ERR_INVALID_ARG
+    assert L.lk_server_create(None, None, C.byref(out)) == lk.LK_ERR_INVALID_ARG
+    assert L.lk_pyramid_destroy(None) == lk.LK_ERR_INVALID_ARG
+    assert L.lk_server_poll(None, 1, None, None, None, None, None) == lk.LK_ERR_INVALID_ARG
+    L.lk_context_destroy(None)          # a no-op
+    L.lk_server_destroy(None)
+
+
+def test_struct_sizes_match_the_header(lk):
+    # the ctypes mirrors must have the C layout (checked by size)
+    assert C.sizeof(lk.lk_params) == 32
+    assert C.sizeof(lk.lk_pair) == 32
+    assert C.sizeof(lk.lk_exec_config) == 16
+    assert C.sizeof(lk.lk_timing) == 24

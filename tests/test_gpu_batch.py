@@ -1,0 +1,137 @@
+"""Batched, prepared (graph / persistent) and plain tracking give the same
+bits: every point's arithmetic is independent of the launch it is in."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2607_01757_amd import lk as _lk
+    return _lk
+
+
+@pytest.fixture(scope="module")
+def ctx(lk):
+    c = lk.lk_context_create(0, 0)
+    yield c
+    lk.lk_context_destroy(c)
+
+
+RES = ((160, 120), (333, 251), (640, 480), (97, 131))
+
+
+def make_streams(seed, n=6):
+    return synth.batch_streams(seed, n_streams=n, kp_range=(1, 300), resolutions=RES)
+
+
+class Setup:
+    def __init__(self, lk, ctx, streams, storage, win, levels, fb):
+        import torch
+        self.lk, self.ctx = lk, ctx
+        self.prev = [torch.from_numpy(s.prev).cuda() for s in streams]
+        self.next = [torch.from_numpy(s.next).cuda() for s in streams]
+        self.pp = [lk.lk_pyramid_create(ctx, s.width, s.height, levels, storage) for s in streams]
+        self.pn = [lk.lk_pyramid_create(ctx, s.width, s.height, levels, storage) for s in streams]
+        lk.lk_build_pyramids(ctx, self.pp, self.prev)
+        counts = [len(s.pts) for s in streams]
+        self.counts = counts
+        self.offs = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(int)
+        self.n = int(sum(counts))
+        self.pts = torch.from_numpy(np.concatenate([s.pts for s in streams])).cuda()
+        self.params = lk.make_params(win, levels, 30, 0.01, 1e-6, fb)
+        self.pairs = [(a, b, int(o), c) for a, b, o, c in zip(self.pp, self.pn, self.offs, counts)]
+        self.levels = levels
+
+    def outputs(self):
+        return self.lk.outputs(self.n, self.levels, with_iters=True)
+
+    def plain(self):
+        import torch
+        lk = self.lk
+        out = self.outputs()
+        for i, (a, b, o, c) in enumerate(self.pairs):
+            lk.lk_build_pyramid(self.ctx, b, self.next[i])
+            lk.lk_track(self.ctx, a, b, self.pts[o:o + c], None, c, self.params, out[0][o:o + c], out[1][o:o + c],
+                        out[2][o:o + c], out[3][o:o + c])
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in out]
+
+    def close(self):
+        for p in self.pp + self.pn:
+            self.lk.lk_pyramid_destroy(p)
+
+
+def same(a, b):
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+@pytest.mark.parametrize("storage,win,levels,fb", [(0, 21, 3, 0.0), (1, 31, 4, 1.0), (0, 9, 2, 1.0), (1, 21, 3, 0.0)])
+def test_batched_equals_plain_bitwise(lk, ctx, storage, win, levels, fb):
+    import torch
+    st = Setup(lk, ctx, make_streams(storage * 10 + win), storage, win, levels, fb)
+    ref = st.plain()
+    out = st.outputs()
+    lk.lk_build_pyramids(ctx, st.pn, st.next)
+    lk.lk_track_batched(ctx, st.pairs, st.pts, None, st.params, *out)
+    torch.cuda.synchronize()
+    same(ref, [t.cpu().numpy() for t in out])
+    assert (ref[1] == 0).mean() > 0.5
+    st.close()
+
+
+@pytest.mark.parametrize("persistent,bpc,graph", [(0, 0, 0), (0, 0, 1), (1, 1, 1), (1, 4, 0), (1, 16, 1)])
+def test_prepared_batch_equals_plain(lk, ctx, persistent, bpc, graph):
+    import torch
+    st = Setup(lk, ctx, make_streams(7), 0, 21, 3, 1.0)
+    ref = st.plain()
+    out = st.outputs()
+    cfg = lk.lk_exec_config(persistent, bpc, graph, 0)
+    b = lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, st.params, *out, config=cfg)
+    for rep in range(3):
+        for t in out:
+            t.zero_()
+        lk.lk_batch_run(b)
+        torch.cuda.synchronize()
+        same(ref, [t.cpu().numpy() for t in out])
+        # unrelated eager work between graph replays
+        torch.ones(1 << 20, device="cuda").sum().item()
+    lk.lk_batch_destroy(b)
+    st.close()
+
+
+def test_autotuner_picks_a_config_and_keeps_results(lk, ctx):
+    import torch
+    st = Setup(lk, ctx, make_streams(3, n=8), 0, 21, 3, 0.0)
+    ref = st.plain()
+    out = st.outputs()
+    b = lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, st.params, *out)
+    cfg, ms = lk.lk_batch_tune(b, reps=2)
+    assert ms > 0 and cfg.persistent in (0, 1) and cfg.use_graph == 1
+    got = lk.lk_batch_config(b)
+    assert (got.persistent, got.blocks_per_cu) == (cfg.persistent, cfg.blocks_per_cu)
+    for t in out:
+        t.zero_()
+    lk.lk_batch_run(b)
+    torch.cuda.synchronize()
+    same(ref, [t.cpu().numpy() for t in out])
+    lk.lk_batch_destroy(b)
+    st.close()
+
+
+def test_invalid_batch_arguments(lk, ctx):
+    st = Setup(lk, ctx, make_streams(1, n=2), 0, 21, 3, 0.0)
+    out = st.outputs()
+    with pytest.raises(lk.LKError):
+        lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, st.params, *out,
+                           config=lk.lk_exec_config(2, 1, 0, 0))
+    bad = lk.make_params(win=22)
+    with pytest.raises(lk.LKError):
+        lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, bad, *out)
+    st.close()
