@@ -265,6 +265,274 @@ def run_batched(args):
     return result
 
 
+def run_stereo(args, f16):
+    """Stereo sequence: per frame, pyramids of the left and right frames,
+    temporal tracking (left t-1 -> t) and stereo tracking (left -> right),
+    both with a 1 px forward-backward check; 200 keypoints per frame
+    (survivors carried, topped up with new points).  Plain per-frame
+    launches, and the same two pairs as one batch of two."""
+    import torch
+    import synth
+    from paper_2607_01757_amd import lk
+
+    win, levels = (31, 4) if f16 else (21, 4)
+    storage = lk.LK_STORAGE_F16 if f16 else lk.LK_STORAGE_F32
+    nf = args.frames
+    seq = synth.StereoSequence(args.seed, n_frames=max(nf, 2))
+    t_r = time.time()
+    left = [seq.frame(t, 0) for t in range(nf)]
+    right = [seq.frame(t, 1) for t in range(nf)]
+    log("rendered %d stereo frames in %.1fs" % (nf, time.time() - t_r))
+    ctx = lk.lk_context_create(0, 0)
+    W, H = seq.width, seq.height
+    dl = [torch.from_numpy(f).cuda() for f in left]
+    dr = [torch.from_numpy(f).cuda() for f in right]
+    pl = [lk.lk_pyramid_create(ctx, W, H, levels, storage) for _ in range(2)]
+    pr = lk.lk_pyramid_create(ctx, W, H, levels, storage)
+    prm = lk.make_params(win, levels, 30, 0.01, 1e-6, 1.0)
+    N = 200
+    outs = [lk.outputs(N, levels) for _ in range(2)]
+    d_pts = torch.empty((2 * N, 2), dtype=torch.float32, device="cuda")
+    out_all = lk.outputs(2 * N, levels)
+
+    def run(mode, record):
+        rng = np.random.default_rng(args.seed)
+        pts = synth.uniform_points(rng, N, W, H)
+        lk.lk_build_pyramid(ctx, pl[0], dl[0])
+        torch.cuda.synchronize()
+        lat, kp, inputs = [], 0, []
+        t0 = time.perf_counter()
+        for t in range(1, nf):
+            a, b = pl[(t - 1) & 1], pl[t & 1]
+            ts = time.perf_counter()
+            d_pts[:N].copy_(torch.from_numpy(pts))
+            if mode == "plain":
+                lk.lk_build_pyramid(ctx, b, dl[t])
+                lk.lk_build_pyramid(ctx, pr, dr[t])
+                lk.lk_track(ctx, a, b, d_pts[:N], None, N, prm, *outs[0][:3], None)
+                st = outs[0][1].cpu().numpy()
+                q = outs[0][0].cpu().numpy()
+            else:
+                lk.lk_build_pyramids(ctx, [b, pr], [dl[t], dr[t]])
+                lk.lk_track(ctx, a, b, d_pts[:N], None, N, prm, *outs[0][:3], None)
+                st = outs[0][1].cpu().numpy()
+                q = outs[0][0].cpu().numpy()
+            if record:
+                inputs.append((t, pts.copy()))
+            keep = q[st == 0]
+            keep = keep[(keep[:, 0] >= 16) & (keep[:, 0] <= W - 17) & (keep[:, 1] >= 16) & (keep[:, 1] <= H - 17)]
+            new = synth.uniform_points(rng, N - len(keep), W, H)
+            pts = np.concatenate([keep, new]).astype(np.float32)[:N]
+            d_pts[N:].copy_(torch.from_numpy(pts))
+            lk.lk_track(ctx, b, pr, d_pts[N:], None, N, prm, *outs[1][:3], None)
+            _ = outs[1][1].cpu().numpy()
+            lat.append((time.perf_counter() - ts) * 1e3)
+            kp += 2 * N
+        wall = time.perf_counter() - t0
+        return kp / wall, lat, inputs
+
+    run("plain", False)                                   # warm-up
+    kps, lat, inputs = run("plain", True)
+    kps_b, lat_b, _ = run("batch2", False)
+    log("stereo %s: plain %.3g kp/s p50 %.3f ms p99 %.3f ms; left+right pyramids in one launch %.3g kp/s p99 %.3f ms" % (
+        "f16" if f16 else "f32", kps, percentile(lat, 50), percentile(lat, 99), kps_b, percentile(lat_b, 99)))
+    result = {
+        "metric": "tracked keypoints/sec + p50/p99 frame latency (stereo sequence, plain per-frame)",
+        "value": kps, "unit": "keypoints/s", "n_gpus": 1, "steps": nf - 1, "warmup": nf - 1,
+        "ms_per_step": float(np.mean(lat)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16" if f16 else "f32", "data": "synthetic",
+        "config": {"workload": "stereo sequence 752x480, %d frames, 200 keypoints, temporal + left-to-right with "
+                               "FB 1 px, %dx%d, 4 levels, %s storage" % (nf, win, win, "binary16" if f16 else "float32")},
+        "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
+        "batch2": {"value": kps_b, "p50_frame_ms": percentile(lat_b, 50), "p99_frame_ms": percentile(lat_b, 99)},
+    }
+    if f16:
+        # precision of binary16 storage: the temporal pass of a few frames vs
+        # the FP64 oracle without storage rounding
+        import oracle
+        errs = []
+        for (t, p0) in inputs[:args.precision_frames]:
+            a = torch.empty(0)
+            pa = lk.lk_pyramid_create(ctx, W, H, levels, storage)
+            pb = lk.lk_pyramid_create(ctx, W, H, levels, storage)
+            lk.lk_build_pyramid(ctx, pa, dl[t - 1])
+            lk.lk_build_pyramid(ctx, pb, dl[t])
+            d_pts[:N].copy_(torch.from_numpy(p0))
+            lk.lk_track(ctx, pa, pb, d_pts[:N], None, N, prm, *outs[0][:3], None)
+            g_pts, g_st = outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()
+            r = oracle.track(left[t - 1], left[t], p0, win=win, levels=levels, fb_thresh=1.0, min_eig=1e-6,
+                             nthreads=os.cpu_count() or 1)
+            ok = (g_st == 0) & (r.status == 0)
+            errs.extend(np.abs(g_pts[ok] - r.pts[ok]).max(axis=1).tolist())
+            lk.lk_pyramid_destroy(pa)
+            lk.lk_pyramid_destroy(pb)
+            del a
+        result["error_vs_fp64_oracle_px"] = {"max": float(np.max(errs)), "p99": float(np.percentile(errs, 99)),
+                                             "points": len(errs), "frames": args.precision_frames}
+        log("binary16 storage vs FP64 oracle: max %.3g px p99 %.3g px over %d points" % (
+            np.max(errs), np.percentile(errs, 99), len(errs)))
+    for p_ in pl + [pr]:
+        lk.lk_pyramid_destroy(p_)
+    lk.lk_context_destroy(ctx)
+    return result
+
+
+def run_serve(args):
+    """256 camera streams with Poisson arrivals (U[20,30] Hz), resolution per
+    stream from the batched set, U[150,1500] keypoints per frame, binary16
+    storage, 31x31, 4 levels, forward-backward 1 px; then the same arrival
+    trace through plain per-frame float32 launches."""
+    import threading
+
+    import torch
+    import synth
+    from paper_2607_01757_amd import lk
+
+    warm, dur = args.serve_warmup, args.serve_seconds
+    trace = synth.ServingTrace(args.seed, n_streams=args.serve_streams, duration_s=warm + dur)
+    pool = synth.FramePool(args.seed)
+    rng = np.random.default_rng(args.seed)
+    pts = [synth.uniform_points(rng, sp.n_kp, sp.width, sp.height) for sp in trace.streams]
+    log("serving trace: %d streams, %d frames over %.0f s" % (len(trace.streams), len(trace.events), warm + dur))
+    ctx = lk.lk_context_create(0, 0)
+    prm16 = lk.make_params(31, 4, 30, 0.01, 1e-6, 1.0)
+    cfg = lk.server_config(max_streams=len(trace.streams), max_points=1500, levels=4, storage=lk.LK_STORAGE_F16,
+                           params=prm16, max_batch=len(trace.streams), inflight=args.serve_inflight, queue_depth=4,
+                           hbm_budget_bytes=64 << 30)
+    srv = lk.lk_server_create(ctx, cfg)
+    ids = [lk.lk_server_open_stream(srv, sp.width, sp.height) for sp in trace.streams]
+    stats0 = lk.lk_server_get_stats(srv)
+    log("server: %d streams open, %.2f GB resident" % (stats0.open_streams, stats0.resident_bytes / 1e9))
+
+    outstanding = []
+    lock = threading.Lock()
+    done = []
+    stop = [False]
+    out_buf = np.zeros((1500, 2), np.float32)
+    st_buf = np.zeros(1500, np.uint8)
+    rs_buf = np.zeros(1500, np.float32)
+
+    def poller():
+        import ctypes as C
+        n = C.c_int32()
+        tm = lk.lk_timing()
+        while not stop[0] or outstanding:
+            with lock:
+                batch = list(outstanding)
+            if not batch:
+                time.sleep(0.0002)
+                continue
+            for t in batch:
+                rc = lk.lib.lk_server_poll(srv, t, out_buf.ctypes.data, st_buf.ctypes.data, rs_buf.ctypes.data,
+                                           C.byref(n), C.byref(tm))
+                if rc == lk.LK_ERR_NOT_READY:
+                    continue
+                with lock:
+                    outstanding.remove(t)
+                if rc == lk.LK_SUCCESS:
+                    done.append((tm.submit_ns, tm.done_ns, n.value))
+            time.sleep(0.0001)
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    busy = 0
+    for (ts, sid, k) in trace.events:
+        while time.perf_counter() - t0 < ts:
+            time.sleep(0.00005)
+        sp = trace.streams[sid]
+        f = pool.frame(sp.width, sp.height, sid, k)
+        while True:
+            try:
+                t = lk.lk_server_submit(srv, ids[sid], f, pts[sid])
+                break
+            except lk.LKError as e:
+                if e.code != lk.LK_ERR_BUSY:
+                    raise
+                busy += 1
+                time.sleep(0.0002)
+        with lock:
+            outstanding.append(t)
+    stop[0] = True
+    th.join()
+    wall = time.perf_counter() - t0
+    base = min(d[0] for d in done)
+    meas = [d for d in done if d[0] - base >= warm * 1e9 and d[2] > 0]
+    lat = [(d[1] - d[0]) / 1e6 for d in meas]
+    span = (max(d[1] for d in meas) - min(d[0] for d in meas)) / 1e9
+    kp = sum(d[2] for d in meas)
+    stats = lk.lk_server_get_stats(srv)
+    served = {"value": kp / span, "unit": "keypoints/s", "p50_frame_ms": percentile(lat, 50),
+              "p99_frame_ms": percentile(lat, 99), "max_frame_ms": float(max(lat)), "frames": len(meas),
+              "batches": int(stats.batches), "frames_per_batch": stats.frames / max(1, stats.batches),
+              "submit_busy_retries": busy, "wall_s": wall, "dtype": "f16 storage, f32 arithmetic"}
+    log("served: %.3g kp/s p50 %.2f ms p99 %.2f ms, %.1f frames/launch" %
+        (served["value"], served["p50_frame_ms"], served["p99_frame_ms"], served["frames_per_batch"]))
+    lk.lk_server_destroy(srv)
+
+    # plain per-frame float32 launches driven by the same trace, one frame at a time
+    prm32 = lk.make_params(31, 4, 30, 0.01, 1e-6, 1.0)
+    pyr = {}
+    dev_frames = {}
+    pinned = {}
+    d_pts = {}
+    outs = lk.outputs(1500, 4)
+    for sp in trace.streams:
+        pyr[sp.stream] = [lk.lk_pyramid_create(ctx, sp.width, sp.height, 4, lk.LK_STORAGE_F32) for _ in range(2)]
+        dev_frames[sp.stream] = [torch.empty((sp.height, sp.width), dtype=torch.uint8, device="cuda") for _ in range(2)]
+        d_pts[sp.stream] = torch.from_numpy(pts[sp.stream]).cuda()
+    for (w, h) in synth.RESOLUTIONS:
+        pinned[(w, h)] = torch.empty((h, w), dtype=torch.uint8).pin_memory()
+    seen = {}
+    lat2, kp2, t_first, t_last = [], 0, None, None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (ts, sid, k) in trace.events:
+        now = time.perf_counter() - t0
+        if now < ts:
+            time.sleep(ts - now)
+        sp = trace.streams[sid]
+        cur = seen.get(sid, 0)
+        hbuf = pinned[(sp.width, sp.height)]
+        hbuf.numpy()[:] = pool.frame(sp.width, sp.height, sid, k)
+        dev_frames[sid][cur & 1].copy_(hbuf, non_blocking=True)
+        lk.lk_build_pyramid(ctx, pyr[sid][cur & 1], dev_frames[sid][cur & 1])
+        if cur > 0:
+            n = sp.n_kp
+            lk.lk_track(ctx, pyr[sid][(cur - 1) & 1], pyr[sid][cur & 1], d_pts[sid], None, n, prm32,
+                        outs[0], outs[1], outs[2], None)
+            res = outs[0][:n].cpu()
+            _ = res.numpy()
+        torch.cuda.synchronize()
+        tdone = time.perf_counter() - t0
+        seen[sid] = cur + 1
+        if ts >= warm and cur > 0:
+            lat2.append((tdone - ts) * 1e3)
+            kp2 += sp.n_kp
+            t_first = ts if t_first is None else t_first
+            t_last = tdone
+    plain = {"value": kp2 / (t_last - t_first), "unit": "keypoints/s", "p50_frame_ms": percentile(lat2, 50),
+             "p99_frame_ms": percentile(lat2, 99), "max_frame_ms": float(max(lat2)), "frames": len(lat2),
+             "dtype": "f32"}
+    log("plain per-frame: %.3g kp/s p50 %.2f ms p99 %.2f ms" % (plain["value"], plain["p50_frame_ms"],
+                                                                 plain["p99_frame_ms"]))
+    for v in pyr.values():
+        for p_ in v:
+            lk.lk_pyramid_destroy(p_)
+    lk.lk_context_destroy(ctx)
+    return {
+        "metric": "tracked keypoints/sec + p50/p99 frame latency (served, 256 Poisson streams)",
+        "value": served["value"], "unit": "keypoints/s", "n_gpus": 1, "steps": served["frames"], "warmup": warm,
+        "ms_per_step": 1e3 * span / max(1, served["frames"]), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "serving: %d streams, Poisson U[20,30] Hz, resolutions {640x480..1920x1080}, "
+                               "U[150,1500] keypoints, 31x31, 4 levels, FB 1 px, binary16 storage, %g s after %g s "
+                               "warm-up" % (len(trace.streams), dur, warm)},
+        "p50_frame_ms": served["p50_frame_ms"], "p99_frame_ms": served["p99_frame_ms"],
+        "served": served, "plain": plain,
+    }
+
+
 def run_copy(args):
     """Plain device copy of a known size (calibrates rocprof byte counters)."""
     import torch
@@ -282,7 +550,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batched", choices=["batched", "copy"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "stereo", "stereo16", "serve", "copy"])
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--precision-frames", type=int, default=5)
+    ap.add_argument("--serve-streams", type=int, default=256)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-inflight", type=int, default=2)
     ap.add_argument("--streams", type=int, default=64)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-streams", type=int, default=64)
@@ -295,6 +569,10 @@ def main():
         sys.exit(2)
     if args.workload == "copy":
         res = run_copy(args)
+    elif args.workload == "serve":
+        res = run_serve(args)
+    elif args.workload in ("stereo", "stereo16"):
+        res = run_stereo(args, args.workload == "stereo16")
     else:
         res = run_batched(args)
     print(json.dumps(res), flush=True)

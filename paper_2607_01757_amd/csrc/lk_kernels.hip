@@ -438,14 +438,28 @@ __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty
     const Plane P = make_plane<KIND>(L.img, L.pitch, L.w, L.h);
     if constexpr (!PLANES) {
         float *E = TY + G::TW * G::TH;
+        // region inside the level (the common case): no reflection needed
+        const bool inside = tx_lo >= 0 && ty_lo >= 0 && tx_lo + G::SW <= L.w && ty_lo + G::SH <= L.h;
+        if (inside) {
+            const int base = ty_lo * L.pitch + tx_lo;
 #pragma unroll
-        for (int k = 0; k < (G::SW * G::SH + kWave - 1) / kWave; ++k) {
-            const int idx = lane + k * kWave;
-            if (idx < G::SW * G::SH) {
-                const int r = idx / G::SW, c = idx - r * G::SW;
-                const int y = reflect101(clampi(ty_lo + r, -1, L.h), L.h);
-                const int x = reflect101(clampi(tx_lo + c, -1, L.w), L.w);
-                E[idx] = bload<KIND>(P, y * L.pitch + x);
+            for (int k = 0; k < (G::SW * G::SH + kWave - 1) / kWave; ++k) {
+                const int idx = lane + k * kWave;
+                if (idx < G::SW * G::SH) {
+                    const int r = idx / G::SW, c = idx - r * G::SW;
+                    E[idx] = bload<KIND>(P, base + r * L.pitch + c);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < (G::SW * G::SH + kWave - 1) / kWave; ++k) {
+                const int idx = lane + k * kWave;
+                if (idx < G::SW * G::SH) {
+                    const int r = idx / G::SW, c = idx - r * G::SW;
+                    const int y = reflect101(clampi(ty_lo + r, -1, L.h), L.h);
+                    const int x = reflect101(clampi(tx_lo + c, -1, L.w), L.w);
+                    E[idx] = bload<KIND>(P, y * L.pitch + x);
+                }
             }
         }
         wave_lds_sync();
@@ -512,9 +526,20 @@ __device__ __forceinline__ void lane_template(const float *lds, const LaneCfg &l
 
 // Raw taps of the target level with this lane's first tap at (bx, by);
 // indices clamped to the level (bilinear taps replicate the edges).
+// `inside`: the taps of every lane lie inside the level (decided for the
+// whole wavefront by the caller), so no index needs clamping.
 template <class G, int KIND>
-__device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, float (&t)[G::R + 1][G::CW + 1])
+__device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, bool inside,
+                                          float (&t)[G::R + 1][G::CW + 1])
 {
+    if (inside) {
+        const int base = by * P.pitch + bx;
+#pragma unroll
+        for (int i = 0; i <= G::R; ++i)
+#pragma unroll
+            for (int j = 0; j <= G::CW; ++j) t[i][j] = bload<KIND>(P, base + i * P.pitch + j);
+        return;
+    }
     int xs[G::CW + 1];
 #pragma unroll
     for (int j = 0; j <= G::CW; ++j) xs[j] = clampi(bx + j, 0, P.w - 1);
@@ -618,9 +643,11 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             const float fux = floorf(ux), fuy = floorf(uy);
             const int bx = cix + (int)fux, by = ciy + (int)fuy;
             if (bx != jbx || by != jby) {
-                if (l == 0) load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, jt);
-                else if constexpr (ST == LK_STORAGE_F16) load_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, jt);
-                else load_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, jt);
+                const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
+                if (l == 0) load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                else if constexpr (ST == LK_STORAGE_F16)
+                    load_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                else load_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
                 jbx = bx; jby = by;
             }
             const Weights w = bilinear_weights(ux - fux, uy - fuy);
@@ -659,7 +686,9 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         // near the frame before converting (taps are clamped anyway)
         const float fux = fminf(fmaxf(floorf(ux), (float)(-cix - h - 2)), (float)(LJ.w + h + 2 - cix));
         const float fuy = fminf(fmaxf(floorf(uy), (float)(-ciy - h - 2)), (float)(LJ.h + h + 2 - ciy));
-        load_taps<G, K_U8>(PJ, cix + (int)fux - h + lc.c0, ciy + (int)fuy - h + lc.r0, jt);
+        const int bx = cix + (int)fux, by = ciy + (int)fuy;
+        const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
+        load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
         const Weights w = bilinear_weights(ux - fux, uy - fuy);
         float acc = 0.0f;
 #pragma unroll
@@ -767,9 +796,11 @@ void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *coun
         const int owner = (xcd + probe) & 7;
         const int first = (int)((long)a.n * owner / 8), end = (int)((long)a.n * (owner + 1) / 8);
         for (;;) {
-            int w = 0;
-            if (lane == 0) w = atomicAdd(&counters[owner], 1);
-            const int wave = first + __builtin_amdgcn_readlane(w, 0);
+            // every lane takes part in the fetch (lane 0 adds 1, the others 0)
+            // so the index is never defined in a divergent branch; lane 0's
+            // old value is this wavefront's keypoint
+            const int w = __builtin_amdgcn_readfirstlane(atomicAdd(&counters[owner], lane == 0 ? 1 : 0));
+            const int wave = first + w;
             if (wave >= end) break;
             int lo = 0, hi = n_items - 1;
             while (lo < hi) {
