@@ -195,16 +195,26 @@ def run_batched(args):
     ends = wl.out.cpu().numpy()
     f_alg = flops_from_iters(iters, wl.win, False)
 
-    # tracker kernel alone (the dominant kernel), HIP events on the launch stream
-    _, trk = time_steps(wl.track, args.steps, args.warmup)
-    t_trk = float(np.mean(trk)) * 1e-3
-    # pyramid build alone
+    # the step as one prepared batch: new-frame pyramids + all pairs, recorded
+    # into a HIP graph, execution shape chosen by the autotuner
+    step = lk.lk_batch_create(ctx, wl.next_pyr, wl.next_img, wl.pairs, wl.pts, None, wl.params, wl.out, wl.st,
+                              wl.res, None, config=lk.lk_exec_config(0, 4, 1, 0))
+    best, tuned_ms = lk.lk_batch_tune(step, reps=3)
+    log("autotuner: persistent=%d blocks_per_cu=%d (%.3f ms/step while tuning)" %
+        (best.persistent, best.blocks_per_cu, tuned_ms))
+    # the tracker alone, same shape, for the roofline of the dominant kernel
+    trk = lk.lk_batch_create(ctx, [], [], wl.pairs, wl.pts, None, wl.params, wl.out, wl.st, wl.res, None,
+                             config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 1, 0))
+    _, trk_ms = time_steps(lambda: lk.lk_batch_run(trk), args.steps, args.warmup)
+    t_trk = float(np.mean(trk_ms)) * 1e-3
     _, pyr = time_steps(wl.build, args.steps, args.warmup)
-    # whole step
-    wall, per = time_steps(wl.step, args.steps, args.warmup)
+    wall, per = time_steps(lambda: lk.lk_batch_run(step), args.steps, args.warmup)
     kps = wl.n * args.steps / wall
-    log("batched: %.3f ms/step  %.3g kp/s  tracker %.3f ms  pyramids %.3f ms" %
+    log("batched (graph): %.3f ms/step  %.3g kp/s  tracker %.3f ms  pyramids %.3f ms" %
         (wall / args.steps * 1e3, kps, t_trk * 1e3, np.mean(pyr)))
+    # the same step through the unprepared batched calls (tables shipped per call)
+    uw, _ = time_steps(wl.step, args.steps, args.warmup)
+    unprepared = {"value": wl.n * args.steps / uw, "unit": "keypoints/s", "ms_per_step": uw / args.steps * 1e3}
 
     # plain per-frame launches over the same frames
     plain = None
@@ -212,7 +222,8 @@ def run_batched(args):
         def plain_step():
             for i in range(len(streams)):
                 wl.plain_frame(i)
-        pw, pper = time_steps(plain_step, max(2, args.steps // 4), max(1, args.warmup // 2))
+        k = max(2, args.steps // 4)
+        pw, pper = time_steps(plain_step, k, max(1, args.warmup // 2))
         # per-frame latency of the plain path: each frame alone, events around it
         lat = []
         for i in range(len(streams)):
@@ -220,8 +231,7 @@ def run_batched(args):
             a.record(); wl.plain_frame(i); b.record()
             torch.cuda.synchronize()
             lat.append(a.elapsed_time(b))
-        plain = {"value": wl.n * max(2, args.steps // 4) / pw, "unit": "keypoints/s",
-                 "ms_per_step": pw / max(2, args.steps // 4) * 1e3,
+        plain = {"value": wl.n * k / pw, "unit": "keypoints/s", "ms_per_step": pw / k * 1e3,
                  "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99)}
         log("plain: %.3f ms/step  %.3g kp/s" % (plain["ms_per_step"], plain["value"]))
 
@@ -245,21 +255,28 @@ def run_batched(args):
         "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched: 64 streams, resolutions {640x480..1920x1080}, U[150,1500] keypoints, "
-                               "21x21 window, 3 levels, 30 iterations, eps 0.01, float32 storage",
-                   "streams": len(streams), "keypoints_per_step": wl.n, "seed": args.seed},
+                               "21x21 window, 3 levels, 30 iterations, eps 0.01, float32 storage; one step = "
+                               "new-frame pyramids + all pairs in one graph-captured prepared batch",
+                   "streams": len(streams), "keypoints_per_step": wl.n, "seed": args.seed,
+                   "exec": {"persistent": best.persistent, "blocks_per_cu": best.blocks_per_cu,
+                            "use_graph": 1}},
         "p50_frame_ms": percentile(per, 50), "p99_frame_ms": percentile(per, 99),
         "tracked_fraction": float(np.mean(status == 0)),
-        "roofline": {"bound": "alu", "kernel": "k_track_batched", "achieved": f_alg / t_trk / 1e12,
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": f_alg / t_trk / 1e12 / PEAK_FP32_TFLOPS,
-                     "traffic": None, "flops_per_launch": f_alg, "kernel_ms": t_trk * 1e3},
+        "roofline": {"bound": "alu", "kernel": "k_track_%s" % ("persist" if best.persistent else "batched"),
+                     "achieved": f_alg / t_trk / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": f_alg / t_trk / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_launch": f_alg, "kernel_ms": t_trk * 1e3},
         "path_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": b_alg / step_s / 1e9,
                      "frac": b_alg / step_s / 1e9 / PEAK_HBM_GBS},
         "pyramid_ms": float(np.mean(pyr)),
+        "unprepared_batched": unprepared,
         "plain": plain,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(streams, args.cpu_streams, 21, 3, 0.0)
+    lk.lk_batch_destroy(step)
+    lk.lk_batch_destroy(trk)
     wl.close()
     lk.lk_context_destroy(ctx)
     return result

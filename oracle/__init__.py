@@ -16,7 +16,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lk_oracle.c")
-LIB = os.path.join(HERE, "liblkoracle.so")
+# LKO_LIB loads another build of the oracle (the mutation tests point it at
+# deliberately broken copies to show that the pins catch them)
+LIB = os.environ.get("LKO_LIB") or os.path.join(HERE, "liblkoracle.so")
 
 OK, LOST_EIG, LOST_OOB, LOST_FB = 0, 1, 2, 3
 
@@ -43,7 +45,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.environ.get("LKO_LIB") and (not os.path.exists(LIB)
+                                              or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build(force=True)
         L = C.CDLL(LIB)
         dp = C.POINTER(C.c_double)

@@ -1,0 +1,89 @@
+"""The pins catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of oracle/lk_oracle.c (a dropped
+term, a wrong sign, index or weight, a transposed operand, a changed
+border, threshold or rounding rule), builds it, and runs the oracle pins
+against it in a subprocess: the pins must fail for every mutant.  Runs on
+the CPU only; the planted copies never leave a temporary directory.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lk_oracle.c")
+
+MUTANTS = [
+    ("Scharr x sign", "gx[(size_t)y * w + x] = (3.0 * (P(ym, xp) - P(ym, xm))",
+     "gx[(size_t)y * w + x] = (3.0 * (P(ym, xm) - P(ym, xp))"),
+    ("Scharr centre weight", "+ 10.0 * (P(y, xp) - P(y, xm))", "+ 9.0 * (P(y, xp) - P(y, xm))"),
+    ("Scharr y uses x offsets", "gy[(size_t)y * w + x] = (3.0 * (P(yp, xm) - P(ym, xm))",
+     "gy[(size_t)y * w + x] = (3.0 * (P(yp, xp) - P(ym, xm))"),
+    ("binomial weights", "{1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16}",
+     "{1.0 / 16, 5.0 / 16, 4.0 / 16, 5.0 / 16, 1.0 / 16}"),
+    ("decimation phase", "int sy = reflect101(2 * y + j - 2, sh);", "int sy = reflect101(2 * y + j - 1, sh);"),
+    ("reflect-101 replaced by symmetric", "if (i < 0) i = -i;", "if (i < 0) i = -i - 1;"),
+    ("level size floor", "ws[l] = (ws[l - 1] + 1) / 2;", "ws[l] = ws[l - 1] / 2;"),
+    ("bilinear x/y weights swapped",
+     "return (1.0 - a) * (1.0 - b) * img[(size_t)ya * w + xa] + a * (1.0 - b) * img[(size_t)ya * w + xb]",
+     "return (1.0 - a) * (1.0 - b) * img[(size_t)ya * w + xa] + b * (1.0 - a) * img[(size_t)ya * w + xb]"),
+    ("bilinear tap not clamped low", "int xa = clampi(x0, 0, w - 1)", "int xa = clampi(x0, 1, w - 1)"),
+    ("normal matrix cross term dropped", "Gxx += ax * ax; Gxy += ax * ay; Gyy += ay * ay;",
+     "Gxx += ax * ax; Gxy += 0.0; Gyy += ay * ay;"),
+    ("2x2 solve transposed", "double ex = (Gyy * bx - Gxy * by) / det;", "double ex = (Gxx * bx - Gxy * by) / det;"),
+    ("mismatch sign", "bx += e * s->Gx[i * win + j];", "bx -= e * s->Gx[i * win + j];"),
+    ("update sign", "dx += ex; dy += ey;", "dx -= ex; dy -= ey;"),
+    ("level propagation without doubling", "gx = 2.0 * (gx + dx); gy = 2.0 * (gy + dy);",
+     "gx = (gx + dx); gy = (gy + dy);"),
+    ("template at the wrong scale", "const double cx = px * sc, cy = py * sc;",
+     "const double cx = px * sc * 0.999, cy = py * sc;"),
+    ("eigenvalue normalisation", "double meig = lam / ((double)nw * 255.0 * 255.0);",
+     "double meig = lam / ((double)nw * 255.0);"),
+    ("largest instead of smallest eigenvalue", "double lam = 0.5 * (Gxx + Gyy - sqrt(",
+     "double lam = 0.5 * (Gxx + Gyy + sqrt("),
+    ("residual without |.|", "acc += fabs(s->T[i * win + j]", "acc += (s->T[i * win + j]"),
+    ("residual not averaged", "*res = acc / nw;", "*res = acc / win;"),
+    ("convergence on the squared norm", "if (nrm < prm->eps) break;", "if (nrm * nrm < prm->eps) break;"),
+    ("forward-backward threshold ignored", "if (fbd > prm->fb_thresh) st = LKO_LOST_FB;",
+     "if (fbd > 1e9) st = LKO_LOST_FB;"),
+    ("final in-image check dropped", "    if (!(bd >= 0.0)) return LKO_LOST_OOB;\n    return LKO_OK;",
+     "    return LKO_OK;"),
+    ("binary16 rounding truncates", "double r = nearbyint(x / q) * q;", "double r = trunc(x / q) * q;"),
+    ("guess scaled to the wrong level", "double sc = ldexp(1.0, -(L - 1));", "double sc = ldexp(1.0, -L);"),
+]
+
+PINS = ["tests/test_oracle_primitives.py", "tests/test_oracle_tracker.py"]
+
+
+@pytest.fixture(scope="module")
+def workdir():
+    with tempfile.TemporaryDirectory() as d:
+        yield d
+
+
+def test_unmutated_copy_passes(workdir):
+    so = os.path.join(workdir, "ok.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-o", so, SRC, "-lm", "-lpthread"])
+    env = dict(os.environ, LKO_LIB=so)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(workdir, name, old, new):
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site not found: " + name
+    src = os.path.join(workdir, "mut.c")
+    so = os.path.join(workdir, "mut_%d.so" % (abs(hash(name)) % 10 ** 8))
+    open(src, "w").write(text.replace(old, new))
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-w", "-o", so, src, "-lm", "-lpthread"])
+    env = dict(os.environ, LKO_LIB=so)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "pins did not catch: " + name

@@ -139,6 +139,29 @@ def test_integer_shift_exact(d):
     assert np.abs(r2.pts[ok2] - (pts[ok2] + np.array(d, float))).max() < 0.02
 
 
+def test_residual_is_mean_absolute_level0_mismatch():
+    # J = integer shift of I plus a +-3 checkerboard: at the true alignment
+    # every |T - J| is exactly 3, and the checkerboard is orthogonal to the
+    # smooth texture's gradients, so LK stays at the true shift.
+    d = (4, -3)
+    pad = 24
+    canvas = (60 + 0.5 * synth.texture_canvas(200 + 2 * pad, 260 + 2 * pad, 31)).round()
+    prev = canvas[pad:pad + 200, pad:pad + 260]
+    nxt = canvas[pad - d[1]:pad - d[1] + 200, pad - d[0]:pad - d[0] + 260].copy()
+    ys, xs = np.mgrid[0:200, 0:260]
+    nxt += 3.0 * np.where((xs + ys) % 2 == 0, 1.0, -1.0)
+    # integer keypoints: the bilinear weights are (0, 0), so the sampled
+    # checkerboard keeps its full +-3 amplitude at the true alignment
+    pts = np.round(synth.uniform_points(np.random.default_rng(8), 150, 260, 200, border=40)).astype(np.float32)
+    r = oracle.track(prev, nxt, pts, win=21, levels=1, max_iters=1, eps=1e-9, min_eig=0.0,
+                     guess=pts + np.array(d, np.float32))
+    step = np.abs(r.pts - (pts + np.array(d, float))).max(axis=1)
+    near = step < 0.005                     # the single step stayed at the alignment
+    assert near.sum() >= 25
+    # there every |T - J| is 3 up to the blur of the sub-pixel step (< 6 step + texture mismatch)
+    np.testing.assert_allclose(r.residual[near], 3.0, atol=0.1)
+
+
 def smooth_img(w, h, dx=0.0, dy=0.0):
     ys, xs = np.mgrid[0:h, 0:w].astype(np.float64)
     xs, ys = xs - dx, ys - dy
