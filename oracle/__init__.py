@@ -61,6 +61,9 @@ def lib():
         trk = [C.c_void_p, C.c_void_p, C.c_int, C.c_int]
         tail = [dp, dp, C.c_int, C.POINTER(Params), dp, C.POINTER(C.c_uint8), dp,
                 C.POINTER(C.c_int32), dp]
+        L.lko_gftt_response.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, dp]
+        L.lko_gftt.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                               C.c_int, C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_float)]
         L.lko_track_f64.argtypes = trk + tail
         L.lko_track_u8.argtypes = trk + [C.c_int] + tail
         _lib = L
@@ -179,3 +182,29 @@ def track(prev, nxt, pts, guess=None, *, win=21, levels=3, max_iters=30, eps=0.0
     # conv margin is stored relative to eps; expose it in px as well
     mg[:, 2] = mg[:, 2] * eps
     return Result(out, st, res, it, mg)
+
+
+# ------------------------------------------------------------- GFTT
+
+def gftt_response(img, r=1):
+    """Shi-Tomasi response (lambda_min of the raw-Scharr structure tensor)."""
+    a = np.ascontiguousarray(img, dtype=np.uint8)
+    h, w = a.shape
+    out = np.empty((h, w))
+    rc = lib().lko_gftt_response(a.ctypes.data, w, h, w, r, _p(out))
+    if rc != 0:
+        raise ValueError("bad gftt arguments")
+    return out
+
+
+def gftt(img, *, r=1, quality=0.01, min_dist=16, max_corners=200, border=0, occupied=None):
+    """Corners (N x 2 float32, integer pixel positions) in selection order."""
+    a = np.ascontiguousarray(img, dtype=np.uint8)
+    h, w = a.shape
+    occ = None if occupied is None or len(occupied) == 0 else np.ascontiguousarray(occupied, dtype=np.float32)
+    out = np.zeros((max(max_corners, 1), 2), np.float32)
+    n = lib().lko_gftt(a.ctypes.data, w, h, w, r, quality, min_dist, max_corners, border,
+                       _p(occ, C.c_float), 0 if occ is None else len(occ), _p(out, C.c_float))
+    if n < 0:
+        raise ValueError("bad gftt arguments")
+    return out[:n]

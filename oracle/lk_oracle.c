@@ -434,3 +434,117 @@ int lko_track_u8(const uint8_t *prev, const uint8_t *next, int w, int h, int pit
     free(a); free(b);
     return rc;
 }
+
+/* ------------------------------------------------------------------ GFTT
+ * Shi-Tomasi corner detection ("good features to track"), the detector the
+ * paper's GFTT+LK baseline uses to seed and replenish tracks (Sec. IV,
+ * Sec. V-E).  The paper does not define it; the classical definition is
+ * written out here:
+ *   1. raw Scharr gradients (the [3 10 3] x [-1 0 1] stencil without the
+ *      1/32 scale, so they are integers), reflect-101 borders;
+ *   2. structure tensor a = sum gx^2, b = sum gx gy, c = sum gy^2 over the
+ *      (2r+1)^2 block around each pixel, reflect-101 borders, exact integers;
+ *   3. response R = lambda_min = ((a + c) - sqrt((a - c)^2 + 4 b^2)) / 2,
+ *      evaluated in double in exactly this order (no fused operations);
+ *   4. candidates: R > quality * max R and R >= each of its 8 neighbours
+ *      (pixels within `border` of the edge are never candidates);
+ *   5. candidates ordered by R descending, ties by raster index ascending;
+ *      taken greedily while no taken or occupied point lies at squared
+ *      distance < min_dist^2, until max_corners are taken.
+ * Writes the corners (x, y) and returns their count, or -1 on bad input. */
+static long long sq_ll(long long v) { return v * v; }
+
+int lko_gftt_response(const uint8_t *img, int w, int h, int pitch, int r, double *resp)
+{
+    if (!img || !resp || w < 3 || h < 3 || r < 0 || r > 3 || pitch < w) return -1;
+    int *gx = malloc((size_t)w * h * sizeof(int)), *gy = malloc((size_t)w * h * sizeof(int));
+    if (!gx || !gy) { free(gx); free(gy); return -2; }
+    for (int y = 0; y < h; ++y) {
+        int ym = reflect101(y - 1, h), yp = reflect101(y + 1, h);
+        for (int x = 0; x < w; ++x) {
+            int xm = reflect101(x - 1, w), xp = reflect101(x + 1, w);
+#define Q(yy, xx) ((int)img[(size_t)(yy) * pitch + (xx)])
+            gx[(size_t)y * w + x] = 3 * (Q(ym, xp) - Q(ym, xm)) + 10 * (Q(y, xp) - Q(y, xm)) + 3 * (Q(yp, xp) - Q(yp, xm));
+            gy[(size_t)y * w + x] = 3 * (Q(yp, xm) - Q(ym, xm)) + 10 * (Q(yp, x) - Q(ym, x)) + 3 * (Q(yp, xp) - Q(ym, xp));
+#undef Q
+        }
+    }
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            long long a = 0, b = 0, c = 0;
+            for (int j = -r; j <= r; ++j)
+                for (int i = -r; i <= r; ++i) {
+                    size_t o = (size_t)reflect101(y + j, h) * w + reflect101(x + i, w);
+                    a += sq_ll(gx[o]);
+                    b += (long long)gx[o] * gy[o];
+                    c += sq_ll(gy[o]);
+                }
+            volatile double t = (double)(a - c);
+            volatile double u = (double)b;
+            volatile double d1 = t * t;
+            volatile double d2 = 4.0 * u * u;
+            volatile double disc = d1 + d2;
+            volatile double s = sqrt(disc);
+            volatile double tr = (double)(a + c);
+            resp[(size_t)y * w + x] = (tr - s) * 0.5;
+        }
+    free(gx); free(gy);
+    return 0;
+}
+
+typedef struct { double r; int idx; } cand_t;
+
+static int cand_cmp(const void *pa, const void *pb)
+{
+    const cand_t *a = pa, *b = pb;
+    if (a->r > b->r) return -1;
+    if (a->r < b->r) return 1;
+    return a->idx < b->idx ? -1 : (a->idx > b->idx);
+}
+
+int lko_gftt(const uint8_t *img, int w, int h, int pitch, int r, double quality, int min_dist, int max_corners,
+             int border, const float *occupied, int n_occupied, float *out_xy)
+{
+    if (!img || w < 3 || h < 3 || !(quality >= 0.0) || min_dist < 0 || max_corners < 0 || border < 0) return -1;
+    if (n_occupied > 0 && !occupied) return -1;
+    double *R = malloc((size_t)w * h * sizeof(double));
+    cand_t *cand = malloc((size_t)w * h * sizeof(cand_t));
+    int *taken = malloc(((size_t)max_corners + 1) * 2 * sizeof(int));
+    if (!R || !cand || !taken) { free(R); free(cand); free(taken); return -2; }
+    int rc = lko_gftt_response(img, w, h, pitch, r, R);
+    if (rc) { free(R); free(cand); free(taken); return rc; }
+    double rmax = 0.0;
+    for (size_t i = 0; i < (size_t)w * h; ++i) if (R[i] > rmax) rmax = R[i];
+    double thr = quality * rmax;
+    int nc = 0;
+    for (int y = border; y < h - border; ++y)
+        for (int x = border; x < w - border; ++x) {
+            double v = R[(size_t)y * w + x];
+            if (!(v > thr) || !(v > 0.0)) continue;
+            int peak = 1;
+            for (int j = -1; j <= 1 && peak; ++j)
+                for (int i = -1; i <= 1; ++i) {
+                    int yy = y + j, xx = x + i;
+                    if ((i || j) && yy >= 0 && yy < h && xx >= 0 && xx < w && R[(size_t)yy * w + xx] > v) { peak = 0; break; }
+                }
+            if (peak) { cand[nc].r = v; cand[nc].idx = y * w + x; ++nc; }
+        }
+    qsort(cand, nc, sizeof(cand_t), cand_cmp);
+    long long md2 = (long long)min_dist * min_dist;
+    int nt = 0;
+    for (int k = 0; k < nc && nt < max_corners; ++k) {
+        int x = cand[k].idx % w, y = cand[k].idx / w, ok = 1;
+        for (int t = 0; t < nt && ok; ++t)
+            if (sq_ll(x - taken[2 * t]) + sq_ll(y - taken[2 * t + 1]) < md2) ok = 0;
+        for (int t = 0; t < n_occupied && ok; ++t) {
+            double dx = x - occupied[2 * t], dy = y - occupied[2 * t + 1];
+            if (dx * dx + dy * dy < (double)md2) ok = 0;
+        }
+        if (!ok) continue;
+        taken[2 * nt] = x; taken[2 * nt + 1] = y; ++nt;
+    }
+    if (out_xy)
+        for (int t = 0; t < nt; ++t) { out_xy[2 * t] = (float)taken[2 * t]; out_xy[2 * t + 1] = (float)taken[2 * t + 1]; }
+    free(R); free(cand); free(taken);
+    return nt;
+}

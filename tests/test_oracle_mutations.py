@@ -55,7 +55,23 @@ MUTANTS = [
     ("guess scaled to the wrong level", "double sc = ldexp(1.0, -(L - 1));", "double sc = ldexp(1.0, -L);"),
 ]
 
-PINS = ["tests/test_oracle_primitives.py", "tests/test_oracle_tracker.py"]
+GFTT_MUTANTS = [
+    ("gftt Scharr centre weight", "+ 10 * (Q(y, xp) - Q(y, xm))", "+ 9 * (Q(y, xp) - Q(y, xm))"),
+    ("gftt Scharr y column", "10 * (Q(yp, x) - Q(ym, x))", "10 * (Q(yp, xm) - Q(ym, x))"),
+    ("gftt tensor cross term dropped", "b += (long long)gx[o] * gy[o];", "b += 0;"),
+    ("gftt largest eigenvalue", "resp[(size_t)y * w + x] = (tr - s) * 0.5;", "resp[(size_t)y * w + x] = (tr + s) * 0.5;"),
+    ("gftt block one column short", "for (int i = -r; i <= r; ++i) {", "for (int i = -r; i < r; ++i) {"),
+    ("gftt quality threshold ignored", "if (!(v > thr) || !(v > 0.0)) continue;", "if (!(v > 0.0)) continue;"),
+    ("gftt no non-maximum suppression", "R[(size_t)yy * w + xx] > v) { peak = 0; break; }",
+     "R[(size_t)yy * w + xx] > 1e300) { peak = 0; break; }"),
+    ("gftt ascending rank", "if (a->r > b->r) return -1;\n    if (a->r < b->r) return 1;",
+     "if (a->r < b->r) return -1;\n    if (a->r > b->r) return 1;"),
+    ("gftt min distance not squared", "long long md2 = (long long)min_dist * min_dist;", "long long md2 = min_dist;"),
+    ("gftt occupied points ignored", "if (dx * dx + dy * dy < (double)md2) ok = 0;", "if (dx * dx + dy * dy < 0.0) ok = 0;"),
+    ("gftt border not applied", "for (int y = border; y < h - border; ++y)", "for (int y = 0; y < h; ++y)"),
+]
+
+PINS = ["tests/test_oracle_primitives.py", "tests/test_oracle_tracker.py", "tests/test_oracle_gftt.py"]
 
 
 @pytest.fixture(scope="module")
@@ -74,7 +90,7 @@ def test_unmutated_copy_passes(workdir):
     assert r.returncode == 0, r.stdout[-2000:]
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+@pytest.mark.parametrize("name,old,new", MUTANTS + GFTT_MUTANTS, ids=[m[0] for m in MUTANTS + GFTT_MUTANTS])
 def test_pins_catch_mutant(workdir, name, old, new):
     text = open(SRC).read()
     assert text.count(old) == 1, "mutation site not found: " + name
