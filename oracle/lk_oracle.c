@@ -537,7 +537,7 @@ int lko_gftt(const uint8_t *img, int w, int h, int pitch, int r, double quality,
         for (int t = 0; t < nt && ok; ++t)
             if (sq_ll(x - taken[2 * t]) + sq_ll(y - taken[2 * t + 1]) < md2) ok = 0;
         for (int t = 0; t < n_occupied && ok; ++t) {
-            double dx = x - occupied[2 * t], dy = y - occupied[2 * t + 1];
+            double dx = (double)x - (double)occupied[2 * t], dy = (double)y - (double)occupied[2 * t + 1];
             if (dx * dx + dy * dy < (double)md2) ok = 0;
         }
         if (!ok) continue;
