@@ -550,6 +550,79 @@ def run_serve(args):
     }
 
 
+def run_detect(args):
+    """Shi-Tomasi detection over the next frames of the 64-stream batch: a
+    fresh detection (no occupied points) and a top-up that keeps new corners
+    away from each stream's first 100 tracked keypoints."""
+    import torch
+    from paper_2607_01757_amd import lk
+    import oracle
+
+    streams = make_streams(args.streams, args.seed)
+    ctx = lk.lk_context_create(0, 0)
+    imgs = [torch.from_numpy(s.next).cuda() for s in streams]
+    px = sum(s.width * s.height for s in streams)
+    det = lk.lk_detector_create(ctx, len(streams), px)
+    cap = args.gftt_corners
+    prm = lk.gftt_params(1, 30, cap, 0, 0.01)
+    occ = [torch.from_numpy(np.ascontiguousarray(s.pts[:100])).cuda() for s in streams]
+    outs = [torch.empty((cap, 2), dtype=torch.float32, device="cuda") for _ in streams]
+    cnts = torch.empty((len(streams),), dtype=torch.int32, device="cuda")
+
+    def frames(with_occ):
+        return [{"img": im, "out_xy": o, "count": cnts[i:i + 1], **({"occupied": occ[i]} if with_occ else {})}
+                for i, (im, o) in enumerate(zip(imgs, outs))]
+    fresh, topup = frames(False), frames(True)
+    res = {}
+    for name, fr in (("fresh", fresh), ("topup", topup)):
+        wall, per = time_steps(lambda: lk.lk_detect_corners(det, fr, prm), args.steps, args.warmup)
+        res[name] = {"ms_per_step": wall / args.steps * 1e3, "frames_per_s": len(streams) * args.steps / wall,
+                     "mpx_per_s": px * args.steps / wall / 1e6, "corners": int(cnts.sum().item())}
+        log("%s: %.3f ms/step (%d frames)  %.0f frames/s  %d corners" %
+            (name, res[name]["ms_per_step"], len(streams), res[name]["frames_per_s"], res[name]["corners"]))
+    # latency of one frame alone (the 752x480 stream)
+    k = next(i for i, s in enumerate(streams) if (s.width, s.height) == (752, 480))
+    one = [fresh[k]]
+    _, lat = time_steps(lambda: lk.lk_detect_corners(det, one, prm), args.steps, args.warmup)
+    # exactness spot check on two frames
+    lk.lk_detect_corners(det, fresh, prm)
+    torch.cuda.synchronize()
+    n = cnts.cpu().numpy()
+    for i in (0, k):
+        want = oracle.gftt(streams[i].next, r=1, quality=0.01, min_dist=30, max_corners=cap)
+        got = outs[i][:n[i]].cpu().numpy()
+        assert np.array_equal(got, want), "detector differs from the oracle on frame %d" % i
+    # algorithmic operations per pixel (radius 1): Scharr pair 16, tensor
+    # products 3, separable 3x3 sums 12, two integer tensor combinations 2,
+    # NMS 8 compares (41 full-rate ops) + 10 binary64 ops at half rate
+    ops = px * (41 + 2 * 10)
+    t = res["fresh"]["ms_per_step"] * 1e-3
+    result = {
+        "metric": "corner detection frames/sec (batched, 64 streams)", "value": res["fresh"]["frames_per_s"],
+        "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["fresh"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32+f64", "data": "synthetic",
+        "config": {"workload": "Shi-Tomasi detection on the next frames of 64 streams {640x480..1920x1080}: "
+                               "3x3 block, quality 0.01, min distance 30, up to %d corners per frame" % cap,
+                   "streams": len(streams), "pixels_per_step": px},
+        "topup": res["topup"], "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
+        "roofline": {"bound": "alu", "kernel": "k_gftt_peaks+k_gftt_select", "achieved": ops / t / 1e12,
+                     "peak": PEAK_FP32_TFLOPS / 2, "unit": "Tops/s (full-rate VALU lane ops)",
+                     "frac": ops / t / 1e12 / (PEAK_FP32_TFLOPS / 2), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        sample = streams[:8]
+        t0 = time.perf_counter()
+        for s_ in sample:
+            oracle.gftt(s_.next, r=1, quality=0.01, min_dist=30, max_corners=cap)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": len(sample) / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+                                  "sample": "first 8 of the 64 frames, one thread, %.1f s" % dt}
+    lk.lk_detector_destroy(det)
+    lk.lk_context_destroy(ctx)
+    return result
+
+
 def run_copy(args):
     """Plain device copy of a known size (calibrates rocprof byte counters)."""
     import torch
@@ -567,7 +640,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batched", choices=["batched", "stereo", "stereo16", "serve", "copy"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "stereo", "stereo16", "serve", "detect",
+                                                           "copy"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--precision-frames", type=int, default=5)
     ap.add_argument("--serve-streams", type=int, default=256)
@@ -579,6 +653,7 @@ def main():
     ap.add_argument("--cpu-streams", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--gftt-corners", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (streams would be sharded "
@@ -588,6 +663,8 @@ def main():
         res = run_copy(args)
     elif args.workload == "serve":
         res = run_serve(args)
+    elif args.workload == "detect":
+        res = run_detect(args)
     elif args.workload in ("stereo", "stereo16"):
         res = run_stereo(args, args.workload == "stereo16")
     else:

@@ -223,6 +223,58 @@ lk_result lk_batch_tune(lk_batch *b, lk_stream stream, int32_t reps, lk_exec_con
 lk_result lk_batch_config(const lk_batch *b, lk_exec_config *cfg);
 lk_result lk_batch_destroy(lk_batch *b);   /* waits for the batch's work */
 
+/* ---- corner detection (Shi-Tomasi "good features to track") -------------
+ * The paper's GFTT+LK front-end seeds and tops up its tracks with this
+ * detector before LK runs (Sec. IV; the keypoint-count study of Sec. V-E).
+ * The paper does not define it; the classical definition is computed, and
+ * the result is exact (the corners and their order are those of the
+ * definition, bit for bit):
+ *   1. integer Scharr gradients ([3 10 3] x [-1 0 1], unscaled) of the 8-bit
+ *      frame, reflect-101 borders;
+ *   2. per pixel a = sum gx^2, b = sum gx gy, c = sum gy^2 over the
+ *      (2 radius + 1)^2 block around it, reflect-101 borders (integers);
+ *   3. response R = lambda_min = ((a + c) - sqrt((a - c)^2 + 4 b^2)) / 2 in
+ *      binary64, one rounding per operation, in the order t = a - c, t * t,
+ *      (4 b) b, their sum, its square root, (a + c) minus it, times 0.5;
+ *   4. candidates: pixels at least `border` from every edge with R > 0,
+ *      R > quality * max(0, max R over the frame), and R not below any of its
+ *      (up to 8) in-frame neighbours;
+ *   5. candidates in order of R descending, ties by raster index (y w + x)
+ *      ascending, are accepted while no accepted corner and no occupied point
+ *      lies at squared distance < min_dist^2 (occupied points at binary64
+ *      distance from the integer pixel), until max_corners are accepted.
+ * A detector owns a device workspace for up to max_frames frames and
+ * max_pixels pixels per call (16 bytes per pixel plus 16 per frame); calls on
+ * one detector share it, so they must be ordered on one stream (or by the
+ * caller).  lk_detect_corners only enqueues work (one small table copy and
+ * three launches). */
+#define LK_GFTT_MAX_CORNERS 4096
+
+typedef struct {
+    int32_t radius;          /* block half-size, 0..3 */
+    int32_t min_dist;        /* pixels, >= 0 */
+    int32_t max_corners;     /* 0..LK_GFTT_MAX_CORNERS per frame */
+    int32_t border;          /* pixels excluded at every edge, >= 0 */
+    double quality;          /* >= 0, finite */
+} lk_gftt_params;
+
+typedef struct {
+    const uint8_t *img;      /* device, h rows of pitch bytes; w, h in [3, 32768] */
+    int32_t w, h, pitch;
+    int32_t n_occupied;      /* points that block their neighbourhood, >= 0 */
+    const float *occupied;   /* device, n_occupied x 2 (x, y); NULL iff n_occupied == 0 */
+    float *out_xy;           /* device, max_corners x 2: accepted corners in order */
+    int32_t *count;          /* device, one int32: number of corners written */
+    double *response;        /* device, nullable: h x w map of R (row pitch w) */
+} lk_gftt_frame;
+
+typedef struct lk_detector lk_detector;
+
+lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pixels, lk_detector **out);
+lk_result lk_detect_corners(lk_detector *det, const lk_gftt_frame *h_frames, int32_t n_frames,
+                            const lk_gftt_params *params, lk_stream stream);
+lk_result lk_detector_destroy(lk_detector *det);   /* waits for the device */
+
 /* ---- serving (continuous batching over many camera streams) --------------
  * A server owns, per camera stream, device frame buffers and two resident
  * pyramids (the previous frame's and the current one's) plus pinned host

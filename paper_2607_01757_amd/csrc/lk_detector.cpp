@@ -1,0 +1,129 @@
+// Corner detector objects and lk_detect_corners (lk.h): argument checks,
+// the per-call job table and the detector workspace.
+#include "lk_runtime.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace lkmi;
+
+struct lk_detector {
+    lk_context *ctx = nullptr;
+    int32_t max_frames = 0;
+    int64_t max_pixels = 0;
+    void *d_ws = nullptr;            // per-frame counters, then peaks
+    size_t bytes = 0;
+    int32_t *d_counts = nullptr;     // n_peaks of frame f at [4 f]
+    unsigned long long *d_max = nullptr;
+    GfttPeak *d_peaks = nullptr;
+};
+
+extern "C" {
+
+lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pixels, lk_detector **out)
+{
+    if (!ctx || !out) return fail(LK_ERR_INVALID_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    if (max_frames < 1 || max_frames > (1 << 20)) return fail(LK_ERR_INVALID_ARG, "max_frames must be in [1, 2^20]");
+    if (max_pixels < 9 || max_pixels > (int64_t(1) << 34)) return fail(LK_ERR_INVALID_ARG, "max_pixels must be in [9, 2^34]");
+    const size_t cnt_bytes = ((size_t)max_frames * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t max_off = cnt_bytes;
+    const size_t max_bytes = ((size_t)max_frames * sizeof(unsigned long long) + 255) & ~size_t(255);
+    const size_t peaks_off = max_off + max_bytes;
+    const size_t bytes = peaks_off + (size_t)max_pixels * sizeof(GfttPeak);
+    if (ctx->budget && ctx->in_use.load() + bytes > ctx->budget)
+        return fail(LK_ERR_OUT_OF_MEMORY, "detector workspace of %zu bytes exceeds the context budget", bytes);
+    lk_detector *d = new (std::nothrow) lk_detector();
+    if (!d) return fail(LK_ERR_OUT_OF_MEMORY, "host allocation failed");
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = hipMalloc(&d->d_ws, bytes);
+    if (e != hipSuccess) { delete d; return hip_fail(e, "hipMalloc(detector workspace)"); }
+    d->ctx = ctx;
+    d->max_frames = max_frames;
+    d->max_pixels = max_pixels;
+    d->bytes = bytes;
+    d->d_counts = static_cast<int32_t *>(d->d_ws);
+    d->d_max = reinterpret_cast<unsigned long long *>(static_cast<char *>(d->d_ws) + max_off);
+    d->d_peaks = reinterpret_cast<GfttPeak *>(static_cast<char *>(d->d_ws) + peaks_off);
+    ctx->in_use += bytes;
+    *out = d;
+    return LK_SUCCESS;
+}
+
+lk_result lk_detect_corners(lk_detector *det, const lk_gftt_frame *h_frames, int32_t n_frames,
+                            const lk_gftt_params *p, lk_stream stream)
+{
+    if (!det || !p) return fail(LK_ERR_INVALID_ARG, "detector or params is NULL");
+    if (n_frames < 0 || n_frames > det->max_frames)
+        return fail(LK_ERR_INVALID_ARG, "n_frames %d not in [0, %d]", n_frames, det->max_frames);
+    if (n_frames == 0) return LK_SUCCESS;
+    if (!h_frames) return fail(LK_ERR_INVALID_ARG, "h_frames is NULL");
+    if (p->radius < 0 || p->radius > 3) return fail(LK_ERR_INVALID_ARG, "radius must be in [0, 3]");
+    if (p->min_dist < 0 || p->min_dist > 32767) return fail(LK_ERR_INVALID_ARG, "min_dist must be in [0, 32767]");
+    if (p->max_corners < 0 || p->max_corners > LK_GFTT_MAX_CORNERS)
+        return fail(LK_ERR_INVALID_ARG, "max_corners must be in [0, %d]", LK_GFTT_MAX_CORNERS);
+    if (p->border < 0) return fail(LK_ERR_INVALID_ARG, "border must be >= 0");
+    if (!(p->quality >= 0.0) || !std::isfinite(p->quality))
+        return fail(LK_ERR_INVALID_ARG, "quality must be finite and >= 0");
+    std::vector<GfttJob> jobs(n_frames);
+    int64_t pixels = 0;
+    long long tiles = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const lk_gftt_frame &F = h_frames[f];
+        if (!F.img || !F.out_xy || !F.count) return fail(LK_ERR_INVALID_ARG, "frame %d: NULL img, out_xy or count", f);
+        if (F.w < 3 || F.h < 3 || F.w > 32768 || F.h > 32768)
+            return fail(LK_ERR_INVALID_ARG, "frame %d: size %dx%d not in [3, 32768]^2", f, F.w, F.h);
+        if (F.pitch < F.w) return fail(LK_ERR_INVALID_ARG, "frame %d: pitch < width", f);
+        if (F.n_occupied < 0 || (F.n_occupied > 0 && !F.occupied))
+            return fail(LK_ERR_INVALID_ARG, "frame %d: bad occupied points", f);
+        GfttJob &J = jobs[f];
+        J.img = F.img;
+        J.w = F.w;
+        J.h = F.h;
+        J.pitch = F.pitch;
+        J.tiles_x = (F.w + kGfttTileW - 1) / kGfttTileW;
+        J.tile_begin = (int32_t)tiles;
+        J.n_occupied = F.n_occupied;
+        J.occupied = F.occupied;
+        J.peaks = det->d_peaks + pixels;
+        J.n_peaks = det->d_counts + f;
+        J.max_bits = det->d_max + f;
+        J.out_xy = F.out_xy;
+        J.count = F.count;
+        J.response = F.response;
+        pixels += (int64_t)F.w * F.h;
+        tiles += (long long)J.tiles_x * ((F.h + kGfttTileH - 1) / kGfttTileH);
+    }
+    if (pixels > det->max_pixels)
+        return fail(LK_ERR_INVALID_ARG, "%lld pixels exceed the detector's %lld", (long long)pixels,
+                    (long long)det->max_pixels);
+    if (tiles > 0x7FFFFFFFLL) return fail(LK_ERR_INVALID_ARG, "too many tiles");
+    (void)hipSetDevice(det->ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StagingRing::Slot *slot = nullptr;
+    const size_t bytes = jobs.size() * sizeof(GfttJob);
+    lk_result r = det->ctx->staging.acquire(bytes, &slot);
+    if (r != LK_SUCCESS) return r;
+    std::memcpy(slot->host, jobs.data(), bytes);
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(detector jobs)");
+    e = launch_gftt(static_cast<const GfttJob *>(slot->dev), n_frames, (int)tiles, p->radius, p->border, p->quality,
+                    p->min_dist, p->max_corners, s);
+    (void)hipEventRecord(slot->done, s);
+    return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "detector launch");
+}
+
+lk_result lk_detector_destroy(lk_detector *det)
+{
+    if (!det) return fail(LK_ERR_INVALID_ARG, "detector is NULL");
+    (void)hipSetDevice(det->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (det->d_ws) (void)hipFree(det->d_ws);
+    det->ctx->in_use -= det->bytes;
+    delete det;
+    return LK_SUCCESS;
+}
+
+}  // extern "C"

@@ -75,6 +75,33 @@ struct GradJob {
     int32_t tiles_x, tile_begin;
 };
 
+// Corner detection: one local maximum of the response (key = bits of R, which
+// is > 0, then the raster index).
+struct GfttPeak {
+    unsigned long long rbits;
+    uint32_t idx;
+    uint32_t pad;
+};
+
+// One frame of a detection call, with its slices of the detector workspace.
+struct GfttJob {
+    const uint8_t *img;
+    int32_t w, h, pitch;
+    int32_t tiles_x, tile_begin;
+    int32_t n_occupied;
+    const float *occupied;
+    GfttPeak *peaks;                 // capacity w * h
+    int32_t *n_peaks;
+    unsigned long long *max_bits;    // bits of max(0, max R)
+    float *out_xy;
+    int32_t *count;
+    double *response;                // nullable
+};
+
+constexpr int kGfttTileW = 64, kGfttTileH = 16;
+constexpr int kGfttWindow = 2048;             // peaks sorted per selection window
+constexpr int kGfttMaxCorners = LK_GFTT_MAX_CORNERS;
+
 // Tile shapes of the pyramid kernels.
 constexpr int kDownTileW = 64, kDownTileH = 16;
 constexpr int kGradTileW = 64, kGradTileH = 16;
@@ -98,6 +125,9 @@ hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total
 // work counters at d_counters (zeroed by the launch itself).
 hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
                                    int storage, int *d_counters, int blocks_per_cu, int num_cus, hipStream_t stream);
+// Detection of every frame in d_jobs (reset, peaks, selection: three launches).
+hipError_t launch_gftt(const GfttJob *d_jobs, int njobs, int total_tiles, int radius, int border, double quality,
+                       int min_dist, int max_corners, hipStream_t stream);
 hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream);
 
 }  // namespace lkmi

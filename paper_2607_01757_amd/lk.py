@@ -28,7 +28,9 @@ ABI_SYMBOLS = (
     "lk_batch_create", "lk_batch_run", "lk_batch_tune", "lk_batch_config", "lk_batch_destroy",
     "lk_server_create", "lk_server_open_stream", "lk_server_submit", "lk_server_poll", "lk_server_close_stream",
     "lk_server_get_stats", "lk_server_destroy",
+    "lk_detector_create", "lk_detect_corners", "lk_detector_destroy",
 )
+LK_GFTT_MAX_CORNERS = 4096
 
 
 class lk_params(C.Structure):
@@ -71,6 +73,17 @@ class lk_server_stats(C.Structure):
                 ("resident_bytes", C.c_uint64), ("open_streams", C.c_int32), ("reserved", C.c_int32)]
 
 
+class lk_gftt_params(C.Structure):
+    _fields_ = [("radius", C.c_int32), ("min_dist", C.c_int32), ("max_corners", C.c_int32),
+                ("border", C.c_int32), ("quality", C.c_double)]
+
+
+class lk_gftt_frame(C.Structure):
+    _fields_ = [("img", C.c_void_p), ("w", C.c_int32), ("h", C.c_int32), ("pitch", C.c_int32),
+                ("n_occupied", C.c_int32), ("occupied", C.c_void_p), ("out_xy", C.c_void_p),
+                ("count", C.c_void_p), ("response", C.c_void_p)]
+
+
 class LKError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("lk error %d: %s" % (code, msg))
@@ -110,6 +123,9 @@ def _load():
         "lk_server_close_stream": (res, [vp, C.c_uint32]),
         "lk_server_get_stats": (res, [vp, C.POINTER(lk_server_stats)]),
         "lk_server_destroy": (None, [vp]),
+        "lk_detector_create": (res, [vp, i32, C.c_int64, C.POINTER(vp)]),
+        "lk_detect_corners": (res, [vp, C.POINTER(lk_gftt_frame), i32, C.POINTER(lk_gftt_params), vp]),
+        "lk_detector_destroy": (res, [vp]),
     }
     for name, (rt, at) in sig.items():
         f = getattr(lib, name)
@@ -316,7 +332,37 @@ def lk_server_destroy(srv):
     lib.lk_server_destroy(srv)
 
 
+def lk_detector_create(ctx, max_frames: int, max_pixels: int):
+    out = C.c_void_p()
+    _check(lib.lk_detector_create(ctx, max_frames, max_pixels, C.byref(out)))
+    return out
+
+
+def lk_detect_corners(det, frames, params: lk_gftt_params, stream=None):
+    """frames: sequence of dicts with img (2-D uint8 CUDA tensor), out_xy
+    (float32 CUDA tensor, max_corners x 2), count (int32 CUDA tensor, 1) and
+    optionally occupied (float32 CUDA tensor, n x 2), response (float64 CUDA
+    tensor, h x w) and pitch."""
+    n = len(frames)
+    F = (lk_gftt_frame * max(n, 1))()
+    for i, f in enumerate(frames):
+        img = f["img"]
+        occ = f.get("occupied")
+        F[i] = lk_gftt_frame(_ptr(img), img.shape[1], img.shape[0], f.get("pitch", img.stride(0)),
+                             0 if occ is None else occ.shape[0], _ptr(occ), _ptr(f["out_xy"]), _ptr(f["count"]),
+                             _ptr(f.get("response")))
+    _check(lib.lk_detect_corners(det, F, n, C.byref(params), _stream(stream)))
+
+
+def lk_detector_destroy(det):
+    _check(lib.lk_detector_destroy(det))
+
+
 # ---------------------------------------------------------------- helpers
+
+def gftt_params(radius=1, min_dist=30, max_corners=200, border=0, quality=0.01) -> lk_gftt_params:
+    return lk_gftt_params(radius, min_dist, max_corners, border, quality)
+
 
 def server_config(max_streams=256, max_points=1500, levels=4, storage=LK_STORAGE_F16, params=None,
                   max_batch=256, inflight=2, queue_depth=4, hbm_budget_bytes=64 << 30) -> lk_server_config:

@@ -20,6 +20,8 @@ STRUCTS = {
                          "queue_depth", "reserved", "hbm_budget_bytes"],
     "lk_timing": ["submit_ns", "launch_ns", "done_ns"],
     "lk_server_stats": ["frames", "batches", "points", "resident_bytes", "open_streams", "reserved"],
+    "lk_gftt_params": ["radius", "min_dist", "max_corners", "border", "quality"],
+    "lk_gftt_frame": ["img", "w", "h", "pitch", "n_occupied", "occupied", "out_xy", "count", "response"],
 }
 
 
