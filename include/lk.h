@@ -244,7 +244,7 @@ lk_result lk_batch_destroy(lk_batch *b);   /* waits for the batch's work */
  *      lies at squared distance < min_dist^2 (occupied points at binary64
  *      distance from the integer pixel), until max_corners are accepted.
  * A detector owns a device workspace for up to max_frames frames and
- * max_pixels pixels per call (16 bytes per pixel plus 16 per frame); calls on
+ * max_pixels pixels per call (32 bytes per pixel plus 16 per frame); calls on
  * one detector share it, so they must be ordered on one stream (or by the
  * caller).  lk_detect_corners only enqueues work (one small table copy and
  * three launches). */

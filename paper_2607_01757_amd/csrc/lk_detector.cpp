@@ -3,6 +3,7 @@
 #include "lk_runtime.h"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -13,11 +14,12 @@ struct lk_detector {
     lk_context *ctx = nullptr;
     int32_t max_frames = 0;
     int64_t max_pixels = 0;
-    void *d_ws = nullptr;            // per-frame counters, then peaks
+    void *d_ws = nullptr;            // per-frame counters and maxima, then peaks, then candidates
     size_t bytes = 0;
-    int32_t *d_counts = nullptr;     // n_peaks of frame f at [4 f]
+    int32_t *d_counts = nullptr;     // n_peaks of frame f at [2 f], n_cand at [2 f + 1]
     unsigned long long *d_max = nullptr;
     GfttPeak *d_peaks = nullptr;
+    GfttPeak *d_cand = nullptr;
 };
 
 extern "C" {
@@ -28,11 +30,12 @@ lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pi
     *out = nullptr;
     if (max_frames < 1 || max_frames > (1 << 20)) return fail(LK_ERR_INVALID_ARG, "max_frames must be in [1, 2^20]");
     if (max_pixels < 9 || max_pixels > (int64_t(1) << 34)) return fail(LK_ERR_INVALID_ARG, "max_pixels must be in [9, 2^34]");
-    const size_t cnt_bytes = ((size_t)max_frames * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t cnt_bytes = ((size_t)max_frames * 2 * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t max_off = cnt_bytes;
     const size_t max_bytes = ((size_t)max_frames * sizeof(unsigned long long) + 255) & ~size_t(255);
     const size_t peaks_off = max_off + max_bytes;
-    const size_t bytes = peaks_off + (size_t)max_pixels * sizeof(GfttPeak);
+    const size_t cand_off = peaks_off + (size_t)max_pixels * sizeof(GfttPeak);
+    const size_t bytes = cand_off + (size_t)max_pixels * sizeof(GfttPeak);
     if (ctx->budget && ctx->in_use.load() + bytes > ctx->budget)
         return fail(LK_ERR_OUT_OF_MEMORY, "detector workspace of %zu bytes exceeds the context budget", bytes);
     lk_detector *d = new (std::nothrow) lk_detector();
@@ -47,6 +50,7 @@ lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pi
     d->d_counts = static_cast<int32_t *>(d->d_ws);
     d->d_max = reinterpret_cast<unsigned long long *>(static_cast<char *>(d->d_ws) + max_off);
     d->d_peaks = reinterpret_cast<GfttPeak *>(static_cast<char *>(d->d_ws) + peaks_off);
+    d->d_cand = reinterpret_cast<GfttPeak *>(static_cast<char *>(d->d_ws) + cand_off);
     ctx->in_use += bytes;
     *out = d;
     return LK_SUCCESS;
@@ -88,7 +92,9 @@ lk_result lk_detect_corners(lk_detector *det, const lk_gftt_frame *h_frames, int
         J.n_occupied = F.n_occupied;
         J.occupied = F.occupied;
         J.peaks = det->d_peaks + pixels;
-        J.n_peaks = det->d_counts + f;
+        J.n_peaks = det->d_counts + 2 * f;
+        J.cand = det->d_cand + pixels;
+        J.n_cand = det->d_counts + 2 * f + 1;
         J.max_bits = det->d_max + f;
         J.out_xy = F.out_xy;
         J.count = F.count;
@@ -102,15 +108,24 @@ lk_result lk_detect_corners(lk_detector *det, const lk_gftt_frame *h_frames, int
     if (tiles > 0x7FFFFFFFLL) return fail(LK_ERR_INVALID_ARG, "too many tiles");
     (void)hipSetDevice(det->ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // jobs, then the job of every tile
+    std::vector<int32_t> tile_job((size_t)tiles);
+    for (int f = 0; f < n_frames; ++f) {
+        const long long n = (long long)jobs[f].tiles_x * ((jobs[f].h + kGfttTileH - 1) / kGfttTileH);
+        std::fill(tile_job.begin() + jobs[f].tile_begin, tile_job.begin() + jobs[f].tile_begin + n, f);
+    }
     StagingRing::Slot *slot = nullptr;
-    const size_t bytes = jobs.size() * sizeof(GfttJob);
+    const size_t jbytes = (jobs.size() * sizeof(GfttJob) + 15) & ~size_t(15);
+    const size_t bytes = jbytes + tile_job.size() * sizeof(int32_t);
     lk_result r = det->ctx->staging.acquire(bytes, &slot);
     if (r != LK_SUCCESS) return r;
-    std::memcpy(slot->host, jobs.data(), bytes);
+    std::memcpy(slot->host, jobs.data(), jobs.size() * sizeof(GfttJob));
+    std::memcpy(static_cast<char *>(slot->host) + jbytes, tile_job.data(), tile_job.size() * sizeof(int32_t));
     hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(detector jobs)");
-    e = launch_gftt(static_cast<const GfttJob *>(slot->dev), n_frames, (int)tiles, p->radius, p->border, p->quality,
-                    p->min_dist, p->max_corners, s);
+    e = launch_gftt(static_cast<const GfttJob *>(slot->dev),
+                    reinterpret_cast<const int32_t *>(static_cast<const char *>(slot->dev) + jbytes), n_frames,
+                    (int)tiles, p->radius, p->border, p->quality, p->min_dist, p->max_corners, s);
     (void)hipEventRecord(slot->done, s);
     return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "detector launch");
 }

@@ -5,19 +5,20 @@
 // quality threshold, greedy minimum-distance selection in rank order) is the
 // one stated in lk.h; results are exact, not approximations of it.
 //
-// Three launches per call, all frames of the call at once:
+// Four launches per call, all frames of the call at once:
 //   k_gftt_reset   zero the per-frame peak counters and maxima (a fill kernel,
 //                  safe under graph capture);
 //   k_gftt_peaks   one 64x16 tile per workgroup: the frame window with a halo
-//                  is staged in LDS, gradients, box sums and the response are
-//                  formed there, every in-frame 3x3 local maximum with R > 0
-//                  is appended to the frame's peak list and the frame maximum
-//                  is raised with one atomic per workgroup;
+//                  is staged in LDS, gradients, block sums and the response
+//                  are formed there, every in-frame 3x3 local maximum with
+//                  R > 0 is appended to the frame's peak list and the frame
+//                  maximum is raised with one atomic per workgroup;
+//   k_gftt_compact keeps the peaks above the quality threshold;
 //   k_gftt_select  one workgroup per frame: the quality threshold follows
 //                  from the maximum; windows of the best remaining peaks are
 //                  found by radix selection on the 96-bit rank key (R bits,
 //                  then the complemented raster index), sorted in LDS, and
-//                  accepted 256 at a time against the corners taken so far
+//                  accepted 512 at a time against the corners taken so far
 //                  and the occupied points.  The acceptance within a chunk
 //                  resolves the greedy rule exactly (a candidate is taken
 //                  iff no better candidate that is taken lies too close).
@@ -55,95 +56,85 @@ __device__ __forceinline__ double min_eig(int32_t a, int32_t b, int32_t c)
     return (tr - s) * 0.5;
 }
 
-__device__ __forceinline__ int find_job(const GfttJob *jobs, int njobs, int tile)
-{
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 template <int R>
-struct PeakSmem {
-    static constexpr int IW = TW + 4 + 2 * R, IH = TH + 4 + 2 * R;   // image window
-    static constexpr int GW = TW + 2 + 2 * R, GH = TH + 2 + 2 * R;   // gradients
-    static constexpr int RW = TW + 2, RH = TH + 2;                   // response
-    uint8_t img[IH][IW + 4];
-    int16_t gx[GH][GW], gy[GH][GW];
-    int32_t ha[GH][RW], hb[GH][RW], hc[GH][RW];
+struct alignas(16) PeakSmem {
+    static constexpr int IH = TH + 4 + 2 * R, IW = 96;               // frame rows y0-2-R.., columns x0-16..
+    static constexpr int GW = TW + 2 + 2 * R, GH = TH + 2 + 2 * R;   // gradients from (x0-1-R, y0-1-R)
+    static constexpr int RW = TW + 2, RH = TH + 2;                   // responses from (x0-1, y0-1)
+    uint8_t img[IH][IW];
+    uint32_t g[GH][GW];            // gx | gy << 16, both int16
     double r[RH][RW];
     uint32_t n_local;
     uint32_t base;
     unsigned long long wmax[BLOCK / 64];
 };
 
+__device__ __forceinline__ int reflect1(int i, int n)       // one reflection; n >= 2, -n < i < 2n - 1
+{
+    i = i < 0 ? -i : i;
+    return i >= n ? 2 * (n - 1) - i : i;
+}
+
 template <int R>
-__global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict__ jobs, int njobs, int border)
+__global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict__ jobs,
+                                                      const int32_t *__restrict__ tile_job, int border)
 {
     using S = PeakSmem<R>;
     __shared__ S sm;
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x;
-    const GfttJob &J = jobs[find_job(jobs, njobs, tile)];
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const GfttJob J = jobs[__builtin_amdgcn_readfirstlane(tile_job[tile])];
     const int t = tile - J.tile_begin;
     const int W = J.w, H = J.h;
     const int x0 = (t % J.tiles_x) * TW, y0 = (t / J.tiles_x) * TH;
-    const uint8_t *img = J.img;
 
     if (tid == 0) sm.n_local = 0;
-    // 1. frame window [x0-2-R, x0+TW+2+R) x [y0-2-R, ...): in-frame samples only
-    for (int e = tid; e < S::IH * S::IW; e += BLOCK) {
-        const int j = e / S::IW, i = e - j * S::IW;
-        const int X = x0 - 2 - R + i, Y = y0 - 2 - R + j;
-        uint8_t v = 0;
-        if (X >= 0 && X < W && Y >= 0 && Y < H) v = img[(size_t)Y * J.pitch + X];
-        sm.img[j][i] = v;
+    // 1. frame rows [y0-2-R, y0+TH+2+R) x columns [x0-16, x0+80) as bytes,
+    //    16-byte loads; a sample outside the frame holds its reflect-101
+    //    sample (only those at distance 1 are ever read)
+    {
+        const bool vec_ok = (J.pitch & 15) == 0 && (reinterpret_cast<uintptr_t>(J.img) & 15) == 0;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(J.img), (short)0, J.pitch * H, 0x00020000);
+        for (int e = tid; e < S::IH * (S::IW / 16); e += BLOCK) {
+            const int j = e / (S::IW / 16), c = e - j * (S::IW / 16);
+            const int Y = reflect1(min(max(y0 - 2 - R + j, -2), H + 1), H);
+            const int X0 = x0 - 16 + 16 * c;
+            if (vec_ok && X0 >= 0 && X0 + 16 <= W) {
+                *reinterpret_cast<uint4 *>(&sm.img[j][16 * c]) =
+                    __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, Y * J.pitch + X0, 0, 0));
+            } else {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int X = reflect1(min(max(X0 + k, -2), W + 1), W);
+                    sm.img[j][16 * c + k] = J.img[(size_t)Y * J.pitch + X];
+                }
+            }
+        }
     }
     __syncthreads();
-    // 2. Scharr gradients at the in-frame samples of [x0-1-R, x0+TW+1+R) x ...;
-    //    neighbours outside the frame are reflected (reflect-101) into it
+    // 2. gradients: slot (X, Y) holds the Scharr gradient at the reflect-101
+    //    image (X, Y) of that position, so the block sums below read their
+    //    taps without any reflection.  Only slots the sums can reach are
+    //    formed: X in [-1-R, W+R), Y in [-1-R, H+R).
     for (int e = tid; e < S::GH * S::GW; e += BLOCK) {
         const int j = e / S::GW, i = e - j * S::GW;
         const int X = x0 - 1 - R + i, Y = y0 - 1 - R + j;
-        int16_t vx = 0, vy = 0;
-        if (X >= 0 && X < W && Y >= 0 && Y < H) {
-            const int ox = x0 - 2 - R, oy = y0 - 2 - R;
-            const int xm = reflect101(X - 1, W) - ox, xp = reflect101(X + 1, W) - ox, xc = X - ox;
-            const int ym = reflect101(Y - 1, H) - oy, yp = reflect101(Y + 1, H) - oy, yc = Y - oy;
-            const int a00 = sm.img[ym][xm], a01 = sm.img[ym][xc], a02 = sm.img[ym][xp];
-            const int a10 = sm.img[yc][xm], a12 = sm.img[yc][xp];
-            const int a20 = sm.img[yp][xm], a21 = sm.img[yp][xc], a22 = sm.img[yp][xp];
-            vx = (int16_t)(3 * (a02 - a00) + 10 * (a12 - a10) + 3 * (a22 - a20));
-            vy = (int16_t)(3 * (a20 - a00) + 10 * (a21 - a01) + 3 * (a22 - a02));
+        uint32_t v = 0;
+        if (X >= -1 - R && X < W + R && Y >= -1 - R && Y < H + R) {
+            const int xc = reflect101(X, W) - (x0 - 16), yc = reflect101(Y, H) - (y0 - 2 - R);
+            const int a00 = sm.img[yc - 1][xc - 1], a01 = sm.img[yc - 1][xc], a02 = sm.img[yc - 1][xc + 1];
+            const int a10 = sm.img[yc][xc - 1], a12 = sm.img[yc][xc + 1];
+            const int a20 = sm.img[yc + 1][xc - 1], a21 = sm.img[yc + 1][xc], a22 = sm.img[yc + 1][xc + 1];
+            const int gx = 3 * (a02 - a00) + 10 * (a12 - a10) + 3 * (a22 - a20);
+            const int gy = 3 * (a20 - a00) + 10 * (a21 - a01) + 3 * (a22 - a02);
+            v = (uint32_t)(gx & 0xFFFF) | ((uint32_t)gy << 16);
         }
-        sm.gx[j][i] = vx;
-        sm.gy[j][i] = vy;
+        sm.g[j][i] = v;
     }
     __syncthreads();
-    // 3. horizontal block sums at the response columns, every in-frame gradient row
-    for (int e = tid; e < S::GH * S::RW; e += BLOCK) {
-        const int j = e / S::RW, i = e - j * S::RW;
-        const int X = x0 - 1 + i, Yg = y0 - 1 - R + j;
-        int32_t a = 0, b = 0, c = 0;
-        if (X >= 0 && X < W && Yg >= 0 && Yg < H) {
-#pragma unroll
-            for (int k = -R; k <= R; ++k) {
-                const int gi = reflect101(X + k, W) - (x0 - 1 - R);
-                const int32_t gx = sm.gx[j][gi], gy = sm.gy[j][gi];
-                a += gx * gx;
-                b += gx * gy;
-                c += gy * gy;
-            }
-        }
-        sm.ha[j][i] = a;
-        sm.hb[j][i] = b;
-        sm.hc[j][i] = c;
-    }
-    __syncthreads();
-    // 4. vertical sums and the response on [x0-1, x0+TW+1) x [y0-1, y0+TH+1);
-    //    positions outside the frame never win a comparison
+    // 3. block sums (exact integers) and the response on [x0-1, x0+TW+1) x
+    //    [y0-1, y0+TH+1); positions outside the frame never win a comparison
     for (int e = tid; e < S::RH * S::RW; e += BLOCK) {
         const int j = e / S::RW, i = e - j * S::RW;
         const int X = x0 - 1 + i, Y = y0 - 1 + j;
@@ -151,18 +142,21 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
         if (X >= 0 && X < W && Y >= 0 && Y < H) {
             int32_t a = 0, b = 0, c = 0;
 #pragma unroll
-            for (int k = -R; k <= R; ++k) {
-                const int hj = reflect101(Y + k, H) - (y0 - 1 - R);
-                a += sm.ha[hj][i];
-                b += sm.hb[hj][i];
-                c += sm.hc[hj][i];
-            }
+            for (int dj = 0; dj <= 2 * R; ++dj)
+#pragma unroll
+                for (int di = 0; di <= 2 * R; ++di) {
+                    const uint32_t q = sm.g[j + dj][i + di];
+                    const int32_t gx = (int32_t)(int16_t)(q & 0xFFFF), gy = (int32_t)q >> 16;
+                    a += gx * gx;
+                    b += gx * gy;
+                    c += gy * gy;
+                }
             v = min_eig(a, b, c);
         }
         sm.r[j][i] = v;
     }
     __syncthreads();
-    // 5. maximum, optional response map, peaks
+    // 4. maximum, optional response map, peaks
     double vmax = 0.0;
     int my_n = 0;
     int my_idx[TW * TH / BLOCK];
@@ -214,10 +208,74 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
     }
 }
 
+// ---- threshold --------------------------------------------------------------
+//
+// The threshold needs the frame maximum, known only once every tile is done:
+// this grid keeps the peaks above it (gridDim.x workgroups per frame, one
+// atomic per wavefront).  Their order does not matter: selection orders
+// candidates by the total rank key.
+constexpr int kCompactBlocks = 32;
+
+__global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restrict__ jobs, double quality)
+{
+    __shared__ uint32_t s_cnt[BLOCK / 64], s_base;
+    const GfttJob &J = jobs[blockIdx.y];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int np = *J.n_peaks;
+    const double thr = quality * __longlong_as_double((long long)*J.max_bits);
+    const unsigned long long thr_bits = (unsigned long long)__double_as_longlong(thr);
+    // this workgroup's slice of the frame's peaks, in steps of BLOCK
+    const int per = (np + gridDim.x - 1) / gridDim.x;
+    const int k_lo = min(np, (int)blockIdx.x * per), k_hi = min(np, k_lo + per);
+    uint32_t mine = 0;
+    for (int k0 = k_lo; k0 < k_hi; k0 += BLOCK) {
+        const int k = k0 + threadIdx.x;
+        mine += (k < k_hi && J.peaks[k].rbits > thr_bits) ? 1u : 0u;
+    }
+    // wavefront and workgroup totals, one global atomic
+    uint32_t wsum = mine;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) wsum += __shfl_xor(wsum, o, 64);
+    if (lane == 0) s_cnt[wv] = wsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) tot += s_cnt[w];
+        s_base = tot ? (uint32_t)atomicAdd(J.n_cand, (int)tot) : 0u;
+    }
+    __syncthreads();
+    // write in the same order: wavefronts in turn, lanes by their prefix
+    uint32_t base = s_base;
+    for (int k0 = k_lo; k0 < k_hi; k0 += BLOCK) {
+        const int k = k0 + threadIdx.x;
+        GfttPeak p{};
+        bool keep = false;
+        if (k < k_hi) {
+            p = J.peaks[k];
+            keep = p.rbits > thr_bits;
+        }
+        const unsigned long long m = __ballot(keep);
+        uint32_t wc = (uint32_t)__popcll(m);
+        if (lane == 0) s_cnt[wv] = wc;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            const uint32_t c = s_cnt[w];
+            before += w < wv ? c : 0u;
+            all += c;
+        }
+        if (keep) J.cand[base + before + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = p;
+        base += all;
+        __syncthreads();
+    }
+}
+
 // ---- selection --------------------------------------------------------------
 
 constexpr int CAPW = kGfttWindow;             // window of peaks sorted in LDS
-constexpr int CHUNK = BLOCK;                  // candidates decided together
+constexpr int SBLOCK = 512;                   // threads of the selection workgroup
+constexpr int CHUNK = SBLOCK;                 // candidates decided together
 constexpr int OCC_LDS = 1024;                 // occupied points cached in LDS
 
 struct Key {
@@ -259,13 +317,14 @@ __device__ __forceinline__ Key key_set_byte(Key k, int d, uint32_t v)
     return k;
 }
 
-struct SelSmem {
+struct alignas(16) SelSmem {
     unsigned long long whi[CAPW];
     uint32_t wlo[CAPW];
-    uint32_t taken[kGfttMaxCorners];          // x | y << 16
+    uint32_t taken[kGfttMaxCorners + 16];     // x | y << 16
     float2 occ[OCC_LDS];
     int32_t cx[CHUNK], cy[CHUNK];
-    uint32_t hist[256];
+    uint32_t hist[SBLOCK / 64][256];           // one histogram per wavefront
+    unsigned long long cmask[CHUNK][CHUNK / 64];   // conflicts with better candidates of the chunk
     unsigned long long sel[CHUNK / 64], und[CHUNK / 64];
     uint32_t wcount;
     Key bound;
@@ -273,69 +332,98 @@ struct SelSmem {
     uint32_t need;
 };
 
-__device__ __forceinline__ bool eligible(Key k, unsigned long long thr_bits, bool bounded, Key bound)
+__device__ __forceinline__ bool eligible(Key k, bool bounded, Key bound)
 {
-    return k.hi > thr_bits && (!bounded || key_less(k, bound));
+    return !bounded || key_less(k, bound);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_gftt_select(const GfttJob *__restrict__ jobs, double quality,
-                                                       int min_dist, int max_corners)
+// Slot of this lane among the lanes of its wavefront that set `take`, in an
+// array whose fill counter is *ctr (one atomic per wavefront).
+__device__ __forceinline__ uint32_t wave_append(bool take, uint32_t *ctr)
+{
+    const unsigned long long m = __ballot(take);
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        if (lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+        base = __shfl(base, leader, 64);
+    }
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+}
+
+__global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restrict__ jobs, int min_dist,
+                                                       int max_corners)
 {
     __shared__ SelSmem sm;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const GfttJob &J = jobs[blockIdx.x];
     const int W = J.w;
-    const int np = *J.n_peaks;
-    const double rmax = __longlong_as_double((long long)*J.max_bits);
-    const double thr = quality * rmax;
-    const unsigned long long thr_bits = (unsigned long long)__double_as_longlong(thr);
-    const long long md2 = (long long)min_dist * min_dist;
+    const int np = *J.n_cand;                  // every candidate is above the threshold
+    const int md2 = min_dist * min_dist;
     const double md2d = (double)md2;
-    const GfttPeak *peaks = J.peaks;
+    const bool spaced = min_dist >= 2;         // distinct pixels are always >= 1 apart
+    const GfttPeak *cand = J.cand;
     const int n_occ = J.n_occupied;
 
-    for (int k = tid; k < n_occ && k < OCC_LDS; k += BLOCK) sm.occ[k] = make_float2(J.occupied[2 * k], J.occupied[2 * k + 1]);
-    // eligible peaks in total
-    if (tid == 0) sm.wcount = 0;
-    __syncthreads();
-    {
-        uint32_t c = 0;
-        for (int k = tid; k < np; k += BLOCK) c += peaks[k].rbits > thr_bits;
-        if (c) atomicAdd(&sm.wcount, c);
-    }
-    __syncthreads();
-    int remaining = (int)sm.wcount;
+    for (int k = tid; k < n_occ && k < OCC_LDS; k += SBLOCK) sm.occ[k] = make_float2(J.occupied[2 * k], J.occupied[2 * k + 1]);
+    int remaining = np;
     int nt = 0;
     bool bounded = false;
     Key bound{0, 0};
     __syncthreads();
 
     while (nt < max_corners && remaining > 0) {
-        // ---- the next window: the best min(CAPW, remaining) eligible peaks
+        // ---- the next window: the best min(CAPW, remaining) candidates
         const int wn = remaining < CAPW ? remaining : CAPW;
         Key low{0, 0};                          // window = eligible keys >= low
         if (wn < remaining) {
             uint32_t need = (uint32_t)wn;
             Key prefix{0, 0};
             for (int d = 0; d < 12; ++d) {
-                for (int k = tid; k < 256; k += BLOCK) sm.hist[k] = 0;
+                for (int k = tid; k < (SBLOCK / 64) * 256; k += SBLOCK) (&sm.hist[0][0])[k] = 0;
                 __syncthreads();
-                for (int k = tid; k < np; k += BLOCK) {
-                    const Key key{peaks[k].rbits, ~peaks[k].idx};
-                    if (eligible(key, thr_bits, bounded, bound) && key_prefix_eq(key, prefix, d))
-                        atomicAdd(&sm.hist[key_byte(key, d)], 1u);
+                for (int k0 = 0; k0 < np; k0 += 8 * SBLOCK) {
+                    Key key[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int k = k0 + i * SBLOCK + tid;
+                        key[i] = k < np ? Key{cand[k].rbits, ~cand[k].idx} : Key{0, 0};
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (key[i].hi != 0 && eligible(key[i], bounded, bound) && key_prefix_eq(key[i], prefix, d))
+                            atomicAdd(&sm.hist[wv][key_byte(key[i], d)], 1u);
                 }
                 __syncthreads();
-                if (tid == 0) {
-                    uint32_t cum = 0;
-                    int g = 255;
-                    for (; g > 0; --g) {
-                        if (cum + sm.hist[g] >= need) break;
-                        cum += sm.hist[g];
+                if (wv == 0) {
+                    // lane l holds digits 4l .. 4l+3; suffix sums from the top
+                    uint32_t t[4], ls = 0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        t[i] = 0;
+#pragma unroll
+                        for (int w = 0; w < SBLOCK / 64; ++w) t[i] += sm.hist[w][4 * lane + i];
+                        ls += t[i];
                     }
-                    sm.need = need - cum;
-                    sm.done_flag = (sm.hist[g] == need - cum) ? 1 : 0;
-                    sm.bound = key_set_byte(prefix, d, (uint32_t)g);
+                    uint32_t above = 0;              // sum over lanes > lane
+                    uint32_t run = ls;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t v = __shfl_down(run, o, 64);
+                        if (lane + o < 64) run += v;
+                    }
+                    above = run - ls;
+                    uint32_t cum = above;
+#pragma unroll
+                    for (int i = 3; i >= 0; --i) {
+                        if (cum < need && need <= cum + t[i]) {
+                            sm.need = need - cum;
+                            sm.done_flag = t[i] == need - cum ? 1 : 0;
+                            sm.bound = key_set_byte(prefix, d, (uint32_t)(4 * lane + i));
+                        }
+                        cum += t[i];
+                    }
                 }
                 __syncthreads();
                 need = sm.need;
@@ -349,31 +437,48 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_select(const GfttJob *__restrict
         // ---- gather the window and sort it (descending) in LDS
         if (tid == 0) sm.wcount = 0;
         __syncthreads();
-        for (int k = tid; k < np; k += BLOCK) {
-            const Key key{peaks[k].rbits, ~peaks[k].idx};
-            if (eligible(key, thr_bits, bounded, bound) && !key_less(key, low)) {
-                const uint32_t s = atomicAdd(&sm.wcount, 1u);
-                if (s < (uint32_t)CAPW) {
-                    sm.whi[s] = key.hi;
-                    sm.wlo[s] = key.lo;
+        for (int k0 = 0; k0 < np; k0 += 8 * SBLOCK) {
+            Key key[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = k0 + i * SBLOCK + tid;
+                key[i] = k < np ? Key{cand[k].rbits, ~cand[k].idx} : Key{0, 0};
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const bool take = key[i].hi != 0 && eligible(key[i], bounded, bound) && !key_less(key[i], low);
+                const uint32_t s = wave_append(take, &sm.wcount);
+                if (take && s < (uint32_t)CAPW) {
+                    sm.whi[s] = key[i].hi;
+                    sm.wlo[s] = key[i].lo;
                 }
             }
         }
         __syncthreads();
         int pw = 1;
         while (pw < wn) pw <<= 1;
-        for (int k = wn + tid; k < pw; k += BLOCK) { sm.whi[k] = 0; sm.wlo[k] = 0; }
+        for (int k = wn + tid; k < pw; k += SBLOCK) { sm.whi[k] = 0; sm.wlo[k] = 0; }
         __syncthreads();
+        constexpr int PAIRS = CAPW / 2 / SBLOCK;
         for (int size = 2; size <= pw; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int k = tid; k < pw / 2; k += BLOCK) {
-                    const int lo = 2 * k - (k & (stride - 1));
-                    const int hi = lo + stride;
-                    const bool desc = (lo & size) == 0;
-                    const Key a{sm.whi[lo], sm.wlo[lo]}, b{sm.whi[hi], sm.wlo[hi]};
-                    if (key_less(a, b) == desc) {
-                        sm.whi[lo] = b.hi; sm.wlo[lo] = b.lo;
-                        sm.whi[hi] = a.hi; sm.wlo[hi] = a.lo;
+                int lo[PAIRS];
+                Key a[PAIRS], b[PAIRS];
+#pragma unroll
+                for (int i = 0; i < PAIRS; ++i) {
+                    const int k = tid + i * SBLOCK;
+                    lo[i] = 2 * k - (k & (stride - 1));
+                    if (k < pw / 2) {
+                        a[i] = Key{sm.whi[lo[i]], sm.wlo[lo[i]]};
+                        b[i] = Key{sm.whi[lo[i] + stride], sm.wlo[lo[i] + stride]};
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < PAIRS; ++i) {
+                    const int k = tid + i * SBLOCK;
+                    if (k < pw / 2 && key_less(a[i], b[i]) == ((lo[i] & size) == 0)) {
+                        sm.whi[lo[i]] = b[i].hi; sm.wlo[lo[i]] = b[i].lo;
+                        sm.whi[lo[i] + stride] = a[i].hi; sm.wlo[lo[i] + stride] = a[i].lo;
                     }
                 }
                 __syncthreads();
@@ -389,82 +494,132 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_select(const GfttJob *__restrict
                 const int idx = (int)~sm.wlo[k];
                 y = idx / W;
                 x = idx - y * W;
-                for (int q = 0; q < nt && !blocked; ++q) {
-                    const uint32_t p = sm.taken[q];
-                    const long long dx = x - (int)(p & 0xFFFFu), dy = y - (int)(p >> 16);
-                    if (dx * dx + dy * dy < md2) blocked = true;
+            }
+            // corners taken so far, 16 per step
+            if (spaced && valid) {
+                const uint4 *t4 = reinterpret_cast<const uint4 *>(sm.taken);
+                for (int q = 0; q < nt && !blocked; q += 16) {
+                    uint32_t p[16];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const uint4 u = t4[q / 4 + v];
+                        p[4 * v] = u.x; p[4 * v + 1] = u.y; p[4 * v + 2] = u.z; p[4 * v + 3] = u.w;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int dx = x - (int)(p[i] & 0xFFFFu), dy = y - (int)(p[i] >> 16);
+                        blocked |= (q + i < nt) && (dx * dx + dy * dy < md2);
+                    }
                 }
-                for (int q = 0; q < n_occ && !blocked; ++q) {
-                    const float2 o = q < OCC_LDS ? sm.occ[q] : make_float2(J.occupied[2 * q], J.occupied[2 * q + 1]);
-                    double dx, dy, dd;
+            }
+            // occupied points, 8 per step (binary64 distance)
+            if (valid && n_occ > 0) {
+                const int nl = n_occ < OCC_LDS ? n_occ : OCC_LDS;
+                const float4 *o4 = reinterpret_cast<const float4 *>(sm.occ);
+                for (int q = 0; q < nl && !blocked; q += 8) {
+                    float ox[8], oy[8];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float4 u = o4[q / 2 + v];
+                        ox[2 * v] = u.x; oy[2 * v] = u.y; ox[2 * v + 1] = u.z; oy[2 * v + 1] = u.w;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        double dd;
+                        {
+#pragma clang fp contract(off)
+                            const double dx = (double)x - (double)ox[i], dy = (double)y - (double)oy[i];
+                            dd = dx * dx + dy * dy;
+                        }
+                        blocked |= (q + i < nl) && (dd < md2d);
+                    }
+                }
+                for (int q = OCC_LDS; q < n_occ && !blocked; ++q) {
+                    double dd;
                     {
 #pragma clang fp contract(off)
-                        dx = (double)x - (double)o.x;
-                        dy = (double)y - (double)o.y;
+                        const double dx = (double)x - (double)J.occupied[2 * q], dy = (double)y - (double)J.occupied[2 * q + 1];
                         dd = dx * dx + dy * dy;
                     }
-                    if (dd < md2d) blocked = true;
+                    blocked |= dd < md2d;
                 }
             }
             sm.cx[tid] = x;
             sm.cy[tid] = y;
             __syncthreads();
-            // conflicts with better candidates of this chunk
+            // conflicts with better candidates of this chunk, 8 per step
             unsigned long long m[CHUNK / 64];
 #pragma unroll
             for (int w = 0; w < CHUNK / 64; ++w) m[w] = 0;
-            if (!blocked) {
-                for (int u = 0; u < tid; ++u) {
-                    const long long dx = x - sm.cx[u], dy = y - sm.cy[u];
-                    if (dx * dx + dy * dy < md2) m[u >> 6] |= 1ull << (u & 63);
-                }
-            }
-            const unsigned long long und0 = __ballot(!blocked);
-            if (lane == 0) { sm.und[wv] = und0; sm.sel[wv] = 0; }
-            __syncthreads();
-            // candidates not blocked by earlier corners: taken iff no better
-            // taken candidate conflicts; decided in rounds
-            while (true) {
-                bool any = false;
+            if (!blocked && spaced) {
+                const int4 *x4 = reinterpret_cast<const int4 *>(sm.cx), *y4 = reinterpret_cast<const int4 *>(sm.cy);
+                for (int u0 = 0; u0 < tid; u0 += 8) {
+                    const int4 xa = x4[u0 / 4], xb = x4[u0 / 4 + 1], ya = y4[u0 / 4], yb = y4[u0 / 4 + 1];
+                    const int ux[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+                    const int uy[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
+                    unsigned long long bits = 0;
 #pragma unroll
-                for (int w = 0; w < CHUNK / 64; ++w) any |= sm.und[w] != 0;
-                if (!any) break;
-                const bool mine = (sm.und[wv] >> lane) & 1ull;
-                bool in = false, out = false;
-                if (mine) {
-                    bool hit = false, wait = false;
-#pragma unroll
-                    for (int w = 0; w < CHUNK / 64; ++w) {
-                        hit |= (m[w] & sm.sel[w]) != 0;
-                        wait |= (m[w] & sm.und[w]) != 0;
+                    for (int i = 0; i < 8; ++i) {
+                        const int dx = x - ux[i], dy = y - uy[i];
+                        bits |= (unsigned long long)((u0 + i < tid) && (dx * dx + dy * dy < md2)) << i;
                     }
-                    out = hit;
-                    in = !hit && !wait;
+#pragma unroll
+                    for (int w = 0; w < CHUNK / 64; ++w)
+                        if (w == (u0 >> 6)) m[w] |= bits << (u0 & 63);
                 }
-                const unsigned long long bin = __ballot(in), bout = __ballot(out);
-                __syncthreads();
-                if (lane == 0) {
-                    sm.sel[wv] |= bin;
-                    sm.und[wv] &= ~(bin | bout);
-                }
-                __syncthreads();
             }
+#pragma unroll
+            for (int w = 0; w < CHUNK / 64; ++w) sm.cmask[tid][w] = m[w];
+            {
+                const unsigned long long free_bits = __ballot(!blocked);
+                if (lane == 0) sm.und[wv] = free_bits;
+            }
+            __syncthreads();
+            // wavefront 0 applies the greedy rule in rank order: candidate t
+            // (not blocked by earlier corners) is taken iff no taken
+            // candidate before it in the chunk conflicts with it
+            if (wv == 0 && !spaced) {
+                if (lane < CHUNK / 64) sm.sel[lane] = sm.und[lane];   // nothing conflicts
+            } else if (wv == 0) {
+                unsigned long long sel[CHUNK / 64];
+#pragma unroll
+                for (int g = 0; g < CHUNK / 64; ++g) {
+                    // lane = candidate 64 g + lane: conflicts with taken ones of earlier groups
+                    const int t = 64 * g + lane;
+                    bool hit = false;
+#pragma unroll
+                    for (int w = 0; w < CHUNK / 64; ++w)
+                        if (w < g) hit |= (sm.cmask[t][w] & sel[w]) != 0;
+                    const unsigned long long mg = sm.cmask[t][g];
+                    unsigned long long open = __ballot(!hit) & sm.und[g];
+                    unsigned long long s_g = 0;
+                    while (open) {
+                        const int b = __builtin_ctzll(open);
+                        open &= open - 1;
+                        const unsigned long long mb =
+                            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(mg >> 32), b) << 32)
+                            | (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mg, b);
+                        if ((mb & s_g) == 0) s_g |= 1ull << b;
+                    }
+                    sel[g] = s_g;
+                }
+                if (lane == 0)
+#pragma unroll
+                    for (int g = 0; g < CHUNK / 64; ++g) sm.sel[g] = sel[g];
+            }
+            __syncthreads();
             // the first (max_corners - nt) taken candidates are kept
             int before = 0, total = 0;
 #pragma unroll
             for (int w = 0; w < CHUNK / 64; ++w) {
-                const unsigned long long s = sm.sel[w];
-                total += __popcll(s);
-                if (w < wv) before += __popcll(s);
-                else if (w == wv) before += __popcll(s & ((1ull << lane) - 1));
+                const unsigned long long sw = sm.sel[w];
+                total += __popcll(sw);
+                if (w < wv) before += __popcll(sw);
+                else if (w == wv) before += __popcll(sw & ((1ull << lane) - 1));
             }
             const bool mine = (sm.sel[wv] >> lane) & 1ull;
             const int pos = nt + before;
-            if (mine && pos < max_corners) {
-                sm.taken[pos] = (uint32_t)x | ((uint32_t)y << 16);
-                J.out_xy[2 * pos] = (float)x;
-                J.out_xy[2 * pos + 1] = (float)y;
-            }
+            if (mine && pos < max_corners) sm.taken[pos] = (uint32_t)x | ((uint32_t)y << 16);
             nt = min(nt + total, max_corners);
             __syncthreads();
         }
@@ -472,6 +627,12 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_select(const GfttJob *__restrict
         bounded = true;
         bound = Key{sm.whi[wn - 1], sm.wlo[wn - 1]};
         __syncthreads();
+    }
+    // corners in order, written once
+    for (int q = tid; q < nt; q += SBLOCK) {
+        const uint32_t p = sm.taken[q];
+        J.out_xy[2 * q] = (float)(p & 0xFFFFu);
+        J.out_xy[2 * q + 1] = (float)(p >> 16);
     }
     if (tid == 0) *J.count = nt;
 }
@@ -481,24 +642,26 @@ __global__ void k_gftt_reset(const GfttJob *__restrict__ jobs, int njobs)
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < njobs) {
         *jobs[k].n_peaks = 0;
+        *jobs[k].n_cand = 0;
         *jobs[k].max_bits = 0ull;
     }
 }
 
 }  // namespace
 
-hipError_t launch_gftt(const GfttJob *d_jobs, int njobs, int total_tiles, int radius, int border, double quality,
-                       int min_dist, int max_corners, hipStream_t s)
+hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int radius,
+                       int border, double quality, int min_dist, int max_corners, hipStream_t s)
 {
     if (njobs <= 0) return hipSuccess;
     k_gftt_reset<<<(njobs + 255) / 256, 256, 0, s>>>(d_jobs, njobs);
     switch (radius) {
-    case 0: k_gftt_peaks<0><<<total_tiles, BLOCK, 0, s>>>(d_jobs, njobs, border); break;
-    case 1: k_gftt_peaks<1><<<total_tiles, BLOCK, 0, s>>>(d_jobs, njobs, border); break;
-    case 2: k_gftt_peaks<2><<<total_tiles, BLOCK, 0, s>>>(d_jobs, njobs, border); break;
-    default: k_gftt_peaks<3><<<total_tiles, BLOCK, 0, s>>>(d_jobs, njobs, border); break;
+    case 0: k_gftt_peaks<0><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
+    case 1: k_gftt_peaks<1><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
+    case 2: k_gftt_peaks<2><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
+    default: k_gftt_peaks<3><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     }
-    k_gftt_select<<<njobs, BLOCK, 0, s>>>(d_jobs, quality, min_dist, max_corners);
+    k_gftt_compact<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality);
+    k_gftt_select<<<njobs, SBLOCK, 0, s>>>(d_jobs, min_dist, max_corners);
     return hipGetLastError();
 }
 

@@ -65,6 +65,18 @@ struct DownJob {
     int32_t tiles_x, tile_begin;
 };
 
+// Levels 1 and 2 of one frame from its 8-bit level 0 in one pass: each
+// workgroup makes a 32 x 16 tile of level 2 and the 64 x 32 tile of level 1
+// under it (level 1 with a two-pixel halo stays in LDS).
+struct Pyr12Job {
+    const uint8_t *src;
+    void *dst1, *dst2;
+    int32_t spitch, pitch1, pitch2;   // elements per row
+    int32_t sw, sh, w1, h1, w2, h2;
+    int32_t f16;                      // levels stored as binary16
+    int32_t tiles_x, tile_begin;
+};
+
 // Gradient plane of one level of one frame (LK_STORAGE_F16 only).
 struct GradJob {
     const void *src;
@@ -90,8 +102,10 @@ struct GfttJob {
     int32_t tiles_x, tile_begin;
     int32_t n_occupied;
     const float *occupied;
-    GfttPeak *peaks;                 // capacity w * h
+    GfttPeak *peaks;                 // local maxima with R > 0, capacity w * h
     int32_t *n_peaks;
+    GfttPeak *cand;                  // those above the quality threshold, capacity w * h
+    int32_t *n_cand;
     unsigned long long *max_bits;    // bits of max(0, max R)
     float *out_xy;
     int32_t *count;
@@ -102,9 +116,20 @@ constexpr int kGfttTileW = 64, kGfttTileH = 16;
 constexpr int kGfttWindow = 2048;             // peaks sorted per selection window
 constexpr int kGfttMaxCorners = LK_GFTT_MAX_CORNERS;
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (block b runs on
+// XCD b mod 8).  Renumbering them so that XCD x takes one contiguous range of
+// work items keeps neighbouring tiles (which share halo cache lines) and the
+// keypoints of one frame in one L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Tile shapes of the pyramid kernels.
 constexpr int kDownTileW = 64, kDownTileH = 16;
 constexpr int kGradTileW = 64, kGradTileH = 16;
+constexpr int kP12TileW = 32, kP12TileH = 16;   // level-2 tile of the fused build
 
 // Window-to-lane layouts of the tracker (see lk_kernels.hip).
 enum Layout { LAYOUT_W21 = 0, LAYOUT_W31 = 1, LAYOUT_W63 = 2 };
@@ -112,9 +137,16 @@ int choose_layout(int win);
 
 // Launchers (lk_kernels.hip).  All enqueue on `stream` and return the launch status.
 hipError_t launch_downsample(const DownJob &job, hipStream_t stream);
-hipError_t launch_downsample_batched(const DownJob *d_jobs, int njobs, int total_tiles, hipStream_t stream);
+// Batched launches: workgroup t works on tile t - job.tile_begin of job
+// d_tile_job[t].
+hipError_t launch_downsample_batched(const DownJob *d_jobs, const int32_t *d_tile_job, int total_tiles,
+                                     hipStream_t stream);
+hipError_t launch_pyr12(const Pyr12Job &job, hipStream_t stream);
+hipError_t launch_pyr12_batched(const Pyr12Job *d_jobs, const int32_t *d_tile_job, int total_tiles,
+                                hipStream_t stream);
 hipError_t launch_grad(const GradJob &job, hipStream_t stream);
-hipError_t launch_grad_batched(const GradJob *d_jobs, int njobs, int total_tiles, hipStream_t stream);
+hipError_t launch_grad_batched(const GradJob *d_jobs, const int32_t *d_tile_job, int total_tiles,
+                               hipStream_t stream);
 hipError_t launch_track(const PyrDesc *d_prev, const PyrDesc *d_next, int storage, const TrackArgs &a,
                         hipStream_t stream);
 hipError_t launch_write_desc(PyrDesc *d_dst, const PyrDesc &src, hipStream_t stream);
@@ -126,8 +158,8 @@ hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total
 hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
                                    int storage, int *d_counters, int blocks_per_cu, int num_cus, hipStream_t stream);
 // Detection of every frame in d_jobs (reset, peaks, selection: three launches).
-hipError_t launch_gftt(const GfttJob *d_jobs, int njobs, int total_tiles, int radius, int border, double quality,
-                       int min_dist, int max_corners, hipStream_t stream);
+hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int radius,
+                       int border, double quality, int min_dist, int max_corners, hipStream_t stream);
 hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream);
 
 }  // namespace lkmi

@@ -80,6 +80,15 @@ __device__ __forceinline__ float ldpx(const void *p, int idx)
 
 // =================================================================== pyramid
 
+// The [1 4 6 4 1] / 16 tap sum, one rounding per operation in this order
+// (the same in every pyramid kernel, so fused and per-level builds agree bit
+// for bit; on 8-bit data and their first two levels every step is exact).
+__device__ __forceinline__ float binom5(float q0, float q1, float q2, float q3, float q4)
+{
+#pragma clang fp contract(off)
+    return ((q0 + q4) + 4.0f * (q1 + q3) + 6.0f * q2) * 0.0625f;
+}
+
 constexpr int kInW = 2 * kDownTileW + 3;   // input tile columns incl. halo
 constexpr int kInH = 2 * kDownTileH + 3;
 constexpr int kBufWord3 = 0x00020000;      // buffer resource word 3, gfx9 family: raw 32-bit access
@@ -158,7 +167,7 @@ __device__ void downsample_tile(const DownJob &j, int tile, DownSmem &sm)
     for (int i = threadIdx.x; i < kInH * kDownTileW; i += kThreads) {
         const int r = i / kDownTileW, c = i - r * kDownTileW;
         const float *q = &sm.in[r][2 * c + off];
-        sm.h[r][c] = ((q[0] + q[4]) + 4.0f * (q[1] + q[3]) + 6.0f * q[2]) * 0.0625f;
+        sm.h[r][c] = binom5(q[0], q[1], q[2], q[3], q[4]);
     }
     __syncthreads();
     // vertical: each thread makes 4 consecutive outputs of one row
@@ -167,8 +176,8 @@ __device__ void downsample_tile(const DownJob &j, int tile, DownSmem &sm)
         float v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            v[k] = ((sm.h[2 * r][c + k] + sm.h[2 * r + 4][c + k]) + 4.0f * (sm.h[2 * r + 1][c + k] + sm.h[2 * r + 3][c + k])
-                    + 6.0f * sm.h[2 * r + 2][c + k]) * 0.0625f;
+            v[k] = binom5(sm.h[2 * r][c + k], sm.h[2 * r + 1][c + k], sm.h[2 * r + 2][c + k], sm.h[2 * r + 3][c + k],
+                          sm.h[2 * r + 4][c + k]);
         const int ox = ox0 + c, oy = oy0 + r;
         if (oy < j.dh) {
             if (ox + 3 < j.dw) {
@@ -207,27 +216,190 @@ __device__ void downsample_dispatch(const DownJob &j, int tile)
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_downsample(DownJob j) { downsample_dispatch(j, blockIdx.x); }
-
-__device__ __forceinline__ int find_job_u(const int32_t *first_tile_of, int stride_bytes, int n, int tile)
+__global__ __launch_bounds__(kThreads) void k_downsample(DownJob j)
 {
-    // last job whose tile_begin <= tile (jobs are sorted by tile_begin)
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const int tb = *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(first_tile_of)
-                                                           + (size_t)mid * stride_bytes);
-        if (tb <= tile) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    downsample_dispatch(j, xcd_block(blockIdx.x, gridDim.x));
 }
 
-__global__ __launch_bounds__(kThreads) void k_downsample_batched(const DownJob *jobs, int njobs)
+__global__ __launch_bounds__(kThreads) void k_downsample_batched(const DownJob *jobs, const int32_t *tile_job)
 {
-    const int tile = blockIdx.x;
-    const int jid = uniform_i(find_job_u(&jobs[0].tile_begin, sizeof(DownJob), njobs, tile));
-    const DownJob j = jobs[jid];
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const DownJob j = jobs[uniform_i(tile_job[tile])];
     downsample_dispatch(j, tile - j.tile_begin);
+}
+
+// ------------------------------------------------ levels 1 and 2 in one pass
+//
+// Workgroup = one 32 x 16 tile of level 2 at (ox2, oy2).  Level 1 is formed
+// on the region x1 in [2 ox2 - 2, 2 ox2 + 65), y1 in [2 oy2 - 2, 2 oy2 + 33)
+// (the 64 x 32 tile under the level-2 tile plus the two-pixel halo the
+// level-2 filter needs) from level 0 staged as bytes; the level-1 tile is
+// written, and level 2 is filtered from the region in LDS.  Region entries
+// outside level 1 are never read: the level-2 taps are reflected (reflect-101)
+// into level 1 first, and the reflected positions lie inside the region
+// whenever the level-2 tile is not empty.  Level 1 is rounded to its storage
+// type before level 2 is formed from it, as a per-level build does.
+
+constexpr int kP1W = 2 * kP12TileW + 3, kP1H = 2 * kP12TileH + 3;     // level-1 region 67 x 35
+constexpr int kP0H = 2 * kP1H + 3;                                      // level-0 rows 73
+constexpr int kP0Chunks = 10;                                           // 16-byte chunks per level-0 row
+constexpr int kP0W = 16 * kP0Chunks;                                    // staged level-0 columns 160
+
+struct alignas(16) P12Smem {
+    uint8_t in[kP0H][kP0W];
+    float l1[kP1H][kP1W + 1];
+    float h2[kP1H][kP12TileW + 1];
+};
+
+__device__ __forceinline__ float to_storage(float v, bool f16)
+{
+    return f16 ? __half2float(__float2half_rn(v)) : v;
+}
+
+__device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
+{
+    const int ox2 = (tile % j.tiles_x) * kP12TileW, oy2 = (tile / j.tiles_x) * kP12TileH;
+    const int rx1 = 2 * ox2 - 2, ry1 = 2 * oy2 - 2;          // level-1 region origin
+    const int a0 = 4 * ox2 - 16, sy0 = 2 * ry1 - 2;          // level-0 staging origin (16-byte aligned x)
+    const bool f16 = j.f16 != 0;
+    // 1. level 0 rows [sy0, sy0 + 73) x columns [a0, a0 + 160) as bytes;
+    //    samples outside the frame hold the reflect-101 sample
+    const bool vec_ok = (j.spitch & 15) == 0 && (reinterpret_cast<uintptr_t>(j.src) & 15) == 0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(j.src), (short)0, j.spitch * j.sh, kBufWord3);
+    for (int i = threadIdx.x; i < kP0H * kP0Chunks; i += kThreads) {
+        const int r = i / kP0Chunks, c = i - r * kP0Chunks;
+        const int gy = reflect101(clampi(sy0 + r, -2, j.sh + 1), j.sh);
+        const int x0 = a0 + 16 * c;
+        if (vec_ok && x0 >= 0 && x0 + 16 <= j.sw) {
+            *reinterpret_cast<uint4 *>(&sm.in[r][16 * c]) =
+                __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, gy * j.spitch + x0, 0, 0));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int gx = reflect101(clampi(x0 + k, -2, j.sw + 1), j.sw);
+                sm.in[r][16 * c + k] = j.src[gy * j.spitch + gx];
+            }
+        }
+    }
+    __syncthreads();
+    // 2. level-1 region by column walk: thread = (column, group of rows);
+    //    the horizontal sums of level-0 rows slide down with the outputs
+    {
+        constexpr int G = kThreads / kP1W;                       // 3 row groups
+        constexpr int RPG = (kP1H + G - 1) / G;                  // 12 rows each
+        const int c = threadIdx.x % kP1W, g = threadIdx.x / kP1W;
+        if (g < G) {
+            const int r_lo = g * RPG, r_hi = min(kP1H, r_lo + RPG);
+            // level-1 x1 = rx1 + c has its centre tap at level-0 x = 2 x1,
+            // staged column 2 x1 - a0 = 2 c + 12
+            const uint8_t *col = &sm.in[0][2 * c + 10];
+            auto hsum = [&](int row) {
+                const uint8_t *q = col + row * kP0W;
+                return binom5((float)q[0], (float)q[1], (float)q[2], (float)q[3], (float)q[4]);
+            };
+            // output row r uses level-0 staged rows 2 r .. 2 r + 4
+            float h0 = hsum(2 * r_lo), h1 = hsum(2 * r_lo + 1), h2 = hsum(2 * r_lo + 2);
+            for (int r = r_lo; r < r_hi; ++r) {
+                const float h3 = hsum(2 * r + 3), h4 = hsum(2 * r + 4);
+                sm.l1[r][c] = to_storage(binom5(h0, h1, h2, h3, h4), f16);
+                h0 = h2; h1 = h3; h2 = h4;
+            }
+        }
+    }
+    __syncthreads();
+    // 3. write the level-1 tile (region rows/columns 2 .. 33 / 2 .. 65): each
+    //    thread stores 8 consecutive pixels of one row
+    {
+        const int r = threadIdx.x >> 3, c = (threadIdx.x & 7) * 8;
+        const int y1 = ry1 + 2 + r, x1 = rx1 + 2 + c;
+        if (y1 < j.h1) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = sm.l1[r + 2][c + 2 + k];
+            if (x1 + 7 < j.w1) {
+                if (f16) {
+                    uint4 u;
+                    u.x = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[0], v[1]));
+                    u.y = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[2], v[3]));
+                    u.z = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[4], v[5]));
+                    u.w = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[6], v[7]));
+                    *reinterpret_cast<uint4 *>(static_cast<__half *>(j.dst1) + (size_t)y1 * j.pitch1 + x1) = u;
+                } else {
+                    float *d = static_cast<float *>(j.dst1) + (size_t)y1 * j.pitch1 + x1;
+                    *reinterpret_cast<float4 *>(d) = make_float4(v[0], v[1], v[2], v[3]);
+                    *reinterpret_cast<float4 *>(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (x1 + k < j.w1) {
+                        if (f16) static_cast<__half *>(j.dst1)[(size_t)y1 * j.pitch1 + x1 + k] = __float2half_rn(v[k]);
+                        else static_cast<float *>(j.dst1)[(size_t)y1 * j.pitch1 + x1 + k] = v[k];
+                    }
+            }
+        }
+    }
+    // 4. level-2 horizontal pass at the level-1 rows of the region; taps
+    //    reflected into level 1 (identity away from its left and right edges)
+    const bool x_inside = rx1 >= 0 && rx1 + kP1W <= j.w1;
+    for (int i = threadIdx.x; i < kP1H * kP12TileW; i += kThreads) {
+        const int r = i / kP12TileW, c = i - r * kP12TileW;
+        float v = 0.0f;
+        if (ox2 + c < j.w2) {           // columns past level 2 are never used
+            float q[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const int x1 = rx1 + 2 * c + k;
+                q[k] = sm.l1[r][(x_inside ? x1 : reflect101(x1, j.w1)) - rx1];
+            }
+            v = binom5(q[0], q[1], q[2], q[3], q[4]);
+        }
+        sm.h2[r][c] = v;
+    }
+    __syncthreads();
+    // 5. level-2 vertical pass (taps reflected into level 1) and store: each
+    //    thread makes 2 consecutive pixels of one row
+    {
+        const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 2;
+        const int y2 = oy2 + r, x2 = ox2 + c;
+        if (y2 < j.h2) {
+            float v[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                float q[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const int y1 = 2 * y2 - 2 + k;
+                    q[k] = sm.h2[reflect101(y1, j.h1) - ry1][c + m];
+                }
+                v[m] = binom5(q[0], q[1], q[2], q[3], q[4]);
+            }
+            if (f16) {
+                __half *d = static_cast<__half *>(j.dst2) + (size_t)y2 * j.pitch2 + x2;
+                if (x2 + 1 < j.w2) *reinterpret_cast<__half2 *>(d) = __floats2half2_rn(v[0], v[1]);
+                else if (x2 < j.w2) d[0] = __float2half_rn(v[0]);
+            } else {
+                float *d = static_cast<float *>(j.dst2) + (size_t)y2 * j.pitch2 + x2;
+                if (x2 + 1 < j.w2) *reinterpret_cast<float2 *>(d) = make_float2(v[0], v[1]);
+                else if (x2 < j.w2) d[0] = v[0];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pyr12(Pyr12Job j)
+{
+    __shared__ P12Smem sm;
+    pyr12_tile(j, xcd_block(blockIdx.x, gridDim.x), sm);
+}
+
+__global__ __launch_bounds__(kThreads) void k_pyr12_batched(const Pyr12Job *jobs, const int32_t *tile_job)
+{
+    __shared__ P12Smem sm;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const Pyr12Job j = jobs[uniform_i(tile_job[tile])];
+    pyr12_tile(j, tile - j.tile_begin, sm);
 }
 
 // ------------------------------------------------------ binary16 gradient planes
@@ -269,13 +441,12 @@ __device__ void grad_dispatch(const GradJob &j, int tile)
     else grad_tile<K_F16>(j, tile, sm);
 }
 
-__global__ __launch_bounds__(kThreads) void k_grad(GradJob j) { grad_dispatch(j, blockIdx.x); }
+__global__ __launch_bounds__(kThreads) void k_grad(GradJob j) { grad_dispatch(j, xcd_block(blockIdx.x, gridDim.x)); }
 
-__global__ __launch_bounds__(kThreads) void k_grad_batched(const GradJob *jobs, int njobs)
+__global__ __launch_bounds__(kThreads) void k_grad_batched(const GradJob *jobs, const int32_t *tile_job)
 {
-    const int tile = blockIdx.x;
-    const int jid = uniform_i(find_job_u(&jobs[0].tile_begin, sizeof(GradJob), njobs, tile));
-    const GradJob j = jobs[jid];
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const GradJob j = jobs[uniform_i(tile_job[tile])];
     grad_dispatch(j, tile - j.tile_begin);
 }
 
@@ -357,7 +528,12 @@ struct Geo {
     static constexpr int EXY = ((WMAX + R - 1) / R) * R;
     static constexpr int TW = EXX + 1, TH = EXY + 1;           // bilinear taps
     static constexpr int SW = TW + 2, SH = TH + 2;             // taps plus the Scharr halo
-    static constexpr int LDS = 3 * TW * TH + SW * SH;          // tap planes + staged level, floats per wavefront
+    static constexpr int LDS = SW * SH + 2 * TW * TH;          // staged level + two gradient planes, floats per wave
+    // column walk of the gradient build: lanes are tap columns, GROUPS row
+    // groups side by side, RPG tap rows each
+    static constexpr int CPASS = (TW + 63) / 64;
+    static constexpr int GROUPS = TW <= 64 ? 64 / TW : 1;
+    static constexpr int RPG = (TH + GROUPS - 1) / GROUPS;
 };
 
 // Inactive lanes mirror lane 0's geometry (every address they form is
@@ -408,36 +584,24 @@ __device__ __forceinline__ float bilerp(const Weights &w, float a, float b, floa
     return fmaf(w.w11, d, fmaf(w.w01, c, fmaf(w.w10, b, w.w00 * a)));
 }
 
-__device__ __forceinline__ float scharr_x(const float *e, int i, int sw)
-{
-    return (3.0f * (e[i - sw + 1] - e[i - sw - 1]) + 10.0f * (e[i + 1] - e[i - 1])
-            + 3.0f * (e[i + sw + 1] - e[i + sw - 1])) * 0.03125f;
-}
-
-__device__ __forceinline__ float scharr_y(const float *e, int i, int sw)
-{
-    return (3.0f * (e[i + sw - 1] - e[i - sw - 1]) + 10.0f * (e[i + sw] - e[i - sw])
-            + 3.0f * (e[i + sw + 1] - e[i - sw + 1])) * 0.03125f;
-}
-
-// Tap planes of the template at level l, in LDS: for every tap position
-// (tx_lo + 1 + tc, ty_lo + 1 + tr), tc < TW, tr < TH, the image value and
-// its Scharr gradients.  Positions outside the level hold values that are
-// never read: the lanes read their taps at positions clamped to the level
-// (bilinear taps replicate the edges), and the gradient at a clamped
-// position only uses the level with reflect-101 borders.
+// Template data of level l in LDS.  E (SW x SH): the level region from
+// (tx_lo, ty_lo) with a one-pixel halo around the tap positions; GX, GY
+// (TW x TH): Scharr gradients at tap positions (tx_lo + 1 + tc, ty_lo + 1 +
+// tr).  Entries at positions outside the level hold values that are never
+// read: lanes read taps at positions clamped to the level (bilinear taps
+// replicate the edges), and the gradient at a clamped position only uses the
+// level with reflect-101 borders.
 //
-// Float levels: the level region with a one-pixel halo is staged first
-// (coalesced loads, reflect-101 applied to the addresses), then every tap
-// position's gradients are computed from it.  Binary16 levels: value and
-// stored gradients are read directly.
+// Float levels: E is staged with coalesced loads (reflect-101 applied to the
+// addresses near an edge), then each lane walks one tap column down E with a
+// three-row window and writes the gradients.  Binary16 levels: the value and
+// the stored gradients are read at the clamped tap positions.
 template <class G, int KIND, bool PLANES>
 __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty_lo, int lane, float *lds)
 {
-    float *TI = lds, *TX = TI + G::TW * G::TH, *TY = TX + G::TW * G::TH;
+    float *E = lds, *TX = lds + G::SW * G::SH, *TY = TX + G::TW * G::TH;
     const Plane P = make_plane<KIND>(L.img, L.pitch, L.w, L.h);
     if constexpr (!PLANES) {
-        float *E = TY + G::TW * G::TH;
         // region inside the level (the common case): no reflection needed
         const bool inside = tx_lo >= 0 && ty_lo >= 0 && tx_lo + G::SW <= L.w && ty_lo + G::SH <= L.h;
         if (inside) {
@@ -463,15 +627,31 @@ __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty
             }
         }
         wave_lds_sync();
+        const int grp = lane / G::TW < G::GROUPS ? lane / G::TW : G::GROUPS;   // GROUPS: idle lane
 #pragma unroll
-        for (int k = 0; k < (G::TW * G::TH + kWave - 1) / kWave; ++k) {
-            const int idx = lane + k * kWave;
-            if (idx < G::TW * G::TH) {
-                const int tr = idx / G::TW, tc = idx - tr * G::TW;
-                const int e = (tr + 1) * G::SW + tc + 1;
-                TI[idx] = E[e];
-                TX[idx] = scharr_x(E, e, G::SW);
-                TY[idx] = scharr_y(E, e, G::SW);
+        for (int cp = 0; cp < G::CPASS; ++cp) {
+            const int tc = cp * 64 + (G::CPASS > 1 ? lane : lane - grp * G::TW);
+            const bool col_ok = grp < G::GROUPS && tc < G::TW;
+            const int tcs = col_ok ? tc : 0;                      // idle lanes read a valid column
+            const int tr0 = (grp < G::GROUPS ? grp : 0) * G::RPG;
+            // rows tr, tr+1, tr+2 of E around tap row tr: D = right - left,
+            // S = 3 left + 10 centre + 3 right
+            const float *e = E + tr0 * G::SW + tcs;
+            float d0 = e[2] - e[0], s0 = fmaf(3.0f, e[0] + e[2], 10.0f * e[1]);
+            e += G::SW;
+            float d1 = e[2] - e[0], s1 = fmaf(3.0f, e[0] + e[2], 10.0f * e[1]);
+#pragma unroll
+            for (int t = 0; t < G::RPG; ++t) {
+                e += G::SW;
+                const int tr = tr0 + t;
+                const bool ok = col_ok && tr < G::TH;
+                const float a = ok ? e[0] : 0.0f, b = ok ? e[1] : 0.0f, c = ok ? e[2] : 0.0f;
+                const float d2 = c - a, s2 = fmaf(3.0f, a + c, 10.0f * b);
+                if (ok) {
+                    TX[tr * G::TW + tc] = (3.0f * d0 + 10.0f * d1 + 3.0f * d2) * 0.03125f;
+                    TY[tr * G::TW + tc] = (s2 - s0) * 0.03125f;
+                }
+                d0 = d1; d1 = d2; s0 = s1; s1 = s2;
             }
         }
     } else {
@@ -484,7 +664,7 @@ __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty
                 const int tr = idx / G::TW, tc = idx - tr * G::TW;
                 const int x = clampi(tx_lo + 1 + tc, 0, L.w - 1);
                 const int y = clampi(ty_lo + 1 + tr, 0, L.h - 1);
-                TI[idx] = bload<KIND>(P, y * L.pitch + x);
+                E[(tr + 1) * G::SW + tc + 1] = bload<KIND>(P, y * L.pitch + x);
                 const float2 g = bload_h2(grs, y * L.gpitch + x);
                 TX[idx] = g.x;
                 TY[idx] = g.y;
@@ -503,19 +683,24 @@ __device__ __forceinline__ void lane_template(const float *lds, const LaneCfg &l
                                               float (&T)[G::R][G::CW], float (&GX)[G::R][G::CW],
                                               float (&GY)[G::R][G::CW])
 {
-    const float *TI = lds, *TX = TI + G::TW * G::TH, *TY = TX + G::TW * G::TH;
-    int cc[G::CW + 1], cr[G::R + 1];
+    const float *E = lds, *TX = lds + G::SW * G::SH, *TY = TX + G::TW * G::TH;
+    int cc[G::CW + 1], cr[G::R + 1], er[G::R + 1];
 #pragma unroll
     for (int j = 0; j <= G::CW; ++j) cc[j] = clampi(tx0 + j, 0, lw - 1) - cx0;
 #pragma unroll
-    for (int i = 0; i <= G::R; ++i) cr[i] = (clampi(ty0 + i, 0, lh - 1) - cy0) * G::TW;
+    for (int i = 0; i <= G::R; ++i) {
+        const int r = clampi(ty0 + i, 0, lh - 1) - cy0;
+        cr[i] = r * G::TW;
+        er[i] = (r + 1) * G::SW + 1;
+    }
 #pragma unroll
     for (int i = 0; i < G::R; ++i)
 #pragma unroll
         for (int j = 0; j < G::CW; ++j) {
             const int t00 = cr[i] + cc[j], t10 = cr[i] + cc[j + 1], t01 = cr[i + 1] + cc[j], t11 = cr[i + 1] + cc[j + 1];
+            const int e00 = er[i] + cc[j], e10 = er[i] + cc[j + 1], e01 = er[i + 1] + cc[j], e11 = er[i + 1] + cc[j + 1];
             const bool ok = c_valid(lc, win, i, j);
-            const float v = bilerp(w, TI[t00], TI[t10], TI[t01], TI[t11]);
+            const float v = bilerp(w, E[e00], E[e10], E[e01], E[e11]);
             const float u = bilerp(w, TX[t00], TX[t10], TX[t01], TX[t11]);
             const float q = bilerp(w, TY[t00], TY[t10], TY[t01], TY[t11]);
             T[i][j] = ok ? v : 0.0f;
@@ -744,11 +929,6 @@ __device__ void track_point(const PyrDesc &prev, const PyrDesc &next, const Trac
 // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
 // XCD works on one contiguous range of points (and of frames), which keeps
 // the pyramids it reads in its own L2.
-__device__ __forceinline__ int xcd_block(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
-    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
 
 template <int ST, class G>
 __global__ __launch_bounds__(G::WPB * 64) __attribute__((amdgpu_waves_per_eu(G::OCC)))
@@ -904,10 +1084,26 @@ hipError_t launch_downsample(const DownJob &job, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_downsample_batched(const DownJob *d_jobs, int njobs, int total_tiles, hipStream_t stream)
+hipError_t launch_downsample_batched(const DownJob *d_jobs, const int32_t *d_tile_job, int total_tiles,
+                                     hipStream_t stream)
 {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_downsample_batched, dim3(total_tiles), dim3(kThreads), 0, stream, d_jobs, njobs);
+    hipLaunchKernelGGL(k_downsample_batched, dim3(total_tiles), dim3(kThreads), 0, stream, d_jobs, d_tile_job);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyr12(const Pyr12Job &job, hipStream_t stream)
+{
+    const int tiles = job.tiles_x * ((job.h2 + kP12TileH - 1) / kP12TileH);
+    hipLaunchKernelGGL(k_pyr12, dim3(tiles), dim3(kThreads), 0, stream, job);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyr12_batched(const Pyr12Job *d_jobs, const int32_t *d_tile_job, int total_tiles,
+                                hipStream_t stream)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pyr12_batched, dim3(total_tiles), dim3(kThreads), 0, stream, d_jobs, d_tile_job);
     return hipGetLastError();
 }
 
@@ -918,10 +1114,11 @@ hipError_t launch_grad(const GradJob &job, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_grad_batched(const GradJob *d_jobs, int njobs, int total_tiles, hipStream_t stream)
+hipError_t launch_grad_batched(const GradJob *d_jobs, const int32_t *d_tile_job, int total_tiles,
+                               hipStream_t stream)
 {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_batched, dim3(total_tiles), dim3(kThreads), 0, stream, d_jobs, njobs);
+    hipLaunchKernelGGL(k_grad_batched, dim3(total_tiles), dim3(kThreads), 0, stream, d_jobs, d_tile_job);
     return hipGetLastError();
 }
 

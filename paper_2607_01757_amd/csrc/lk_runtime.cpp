@@ -130,20 +130,36 @@ TrackArgs make_args(const lk_params *p, int n, const float *pts, const float *gu
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Down/grad jobs that build one pyramid from its recorded level 0.
-void pyramid_jobs(const lk_pyramid *p, std::vector<DownJob> *down_by_level, std::vector<GradJob> *grads)
+void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<DownJob> *down_by_level,
+                  std::vector<GradJob> *grads)
 {
     const PyrDesc &d = p->desc;
-    for (int l = 1; l < d.levels; ++l) {
+    const bool f16 = d.storage == LK_STORAGE_F16;
+    int first = 1;
+    if (d.levels >= 3) {
+        Pyr12Job j{};
+        j.src = static_cast<const uint8_t *>(d.lv[0].img);
+        j.dst1 = const_cast<void *>(d.lv[1].img);
+        j.dst2 = const_cast<void *>(d.lv[2].img);
+        j.spitch = d.lv[0].pitch; j.pitch1 = d.lv[1].pitch; j.pitch2 = d.lv[2].pitch;
+        j.sw = d.lv[0].w; j.sh = d.lv[0].h; j.w1 = d.lv[1].w; j.h1 = d.lv[1].h; j.w2 = d.lv[2].w; j.h2 = d.lv[2].h;
+        j.f16 = f16;
+        j.tiles_x = (j.w2 + kP12TileW - 1) / kP12TileW;
+        j.tile_begin = 0;
+        p12->push_back(j);
+        first = 3;
+    }
+    for (int l = first; l < d.levels; ++l) {
         DownJob j{};
         j.src = d.lv[l - 1].img; j.dst = const_cast<void *>(d.lv[l].img);
         j.spitch = d.lv[l - 1].pitch; j.dpitch = d.lv[l].pitch;
         j.sw = d.lv[l - 1].w; j.sh = d.lv[l - 1].h; j.dw = d.lv[l].w; j.dh = d.lv[l].h;
-        j.src_u8 = l == 1; j.dst_f16 = d.storage == LK_STORAGE_F16;
+        j.src_u8 = l == 1; j.dst_f16 = f16;
         j.tiles_x = (j.dw + kDownTileW - 1) / kDownTileW;
         j.tile_begin = 0;
         down_by_level[l].push_back(j);
     }
-    if (d.storage == LK_STORAGE_F16)
+    if (f16)
         for (int l = 0; l < d.levels; ++l) {
             GradJob g{};
             g.src = d.lv[l].img; g.dst = const_cast<__half2 *>(d.lv[l].grad);
@@ -292,17 +308,23 @@ lk_result lk_build_pyramid(lk_context *ctx, lk_pyramid *pyr, const uint8_t *d_im
     hipStream_t s = static_cast<hipStream_t>(stream);
     pyr->desc.lv[0].img = d_img;
     pyr->desc.lv[0].pitch = pitch;
+    std::vector<Pyr12Job> p12;
     std::vector<DownJob> down[LK_MAX_LEVELS];
     std::vector<GradJob> grads;
-    pyramid_jobs(pyr, down, &grads);
+    pyramid_jobs(pyr, &p12, down, &grads);
     {
         hipError_t e = launch_write_desc(pyr->d_desc, pyr->desc, s);
         if (e != hipSuccess) return hip_fail(e, "descriptor write launch");
     }
-    for (int l = 1; l < pyr->desc.levels; ++l) {
-        hipError_t e = launch_downsample(down[l][0], s);
+    for (auto &j : p12) {
+        hipError_t e = launch_pyr12(j, s);
         if (e != hipSuccess) return hip_fail(e, "pyramid kernel launch");
     }
+    for (int l = 1; l < pyr->desc.levels; ++l)
+        for (auto &j : down[l]) {
+            hipError_t e = launch_downsample(j, s);
+            if (e != hipSuccess) return hip_fail(e, "pyramid kernel launch");
+        }
     for (auto &g : grads) {
         hipError_t e = launch_grad(g, s);
         if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
@@ -445,6 +467,31 @@ lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const l
     return check_params(params, min_levels);
 }
 
+namespace {
+
+// Tile numbering of one launch: job k owns tiles [tile_begin, tile_begin +
+// tiles); tj[t] is the job of tile t.
+template <class J>
+void number_tiles(std::vector<J> &jobs, std::vector<int32_t> &tj, int tile_h, int (*rows)(const J &))
+{
+    tj.clear();
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        J &j = jobs[k];
+        j.tile_begin = (int32_t)tj.size();
+        const long long tiles = (long long)j.tiles_x * ((rows(j) + tile_h - 1) / tile_h);
+        tj.insert(tj.end(), (size_t)tiles, (int32_t)k);
+    }
+}
+
+size_t place(size_t *o, size_t bytes)
+{
+    const size_t at = *o;
+    *o = (at + bytes + 15) & ~size_t(15);
+    return at;
+}
+
+}  // namespace
+
 void make_build_tables(lk_pyramid *const *pyrs, int n, BuildTables *t)
 {
     *t = BuildTables{};
@@ -452,40 +499,49 @@ void make_build_tables(lk_pyramid *const *pyrs, int n, BuildTables *t)
     for (int i = 0; i < n; ++i) {
         t->descs[i].dst = pyrs[i]->d_desc;
         t->descs[i].desc = pyrs[i]->desc;
-        pyramid_jobs(pyrs[i], t->down, &t->grads);
+        pyramid_jobs(pyrs[i], &t->p12, t->down, &t->grads);
     }
-    size_t o = t->descs.size() * sizeof(PyrDescWrite);
-    for (int l = 1; l < LK_MAX_LEVELS; ++l) {
-        int tiles = 0;
-        for (auto &j : t->down[l]) { j.tile_begin = tiles; tiles += j.tiles_x * ((j.dh + kDownTileH - 1) / kDownTileH); }
-        t->tiles_down[l] = tiles;
-        t->off_down[l] = o;
-        o += t->down[l].size() * sizeof(DownJob);
-    }
-    for (auto &g : t->grads) { g.tile_begin = t->tiles_grad; t->tiles_grad += g.tiles_x * ((g.h + kGradTileH - 1) / kGradTileH); }
-    t->off_grad = o;
-    o += t->grads.size() * sizeof(GradJob);
+    number_tiles<Pyr12Job>(t->p12, t->tj_p12, kP12TileH, [](const Pyr12Job &j) { return (int)j.h2; });
+    for (int l = 1; l < LK_MAX_LEVELS; ++l)
+        number_tiles<DownJob>(t->down[l], t->tj_down[l], kDownTileH, [](const DownJob &j) { return (int)j.dh; });
+    number_tiles<GradJob>(t->grads, t->tj_grad, kGradTileH, [](const GradJob &j) { return (int)j.h; });
+    size_t o = 0;
+    place(&o, t->descs.size() * sizeof(PyrDescWrite));
+    t->off_p12 = place(&o, t->p12.size() * sizeof(Pyr12Job));
+    for (int l = 1; l < LK_MAX_LEVELS; ++l) t->off_down[l] = place(&o, t->down[l].size() * sizeof(DownJob));
+    t->off_grad = place(&o, t->grads.size() * sizeof(GradJob));
+    t->off_tj_p12 = place(&o, t->tj_p12.size() * sizeof(int32_t));
+    for (int l = 1; l < LK_MAX_LEVELS; ++l) t->off_tj_down[l] = place(&o, t->tj_down[l].size() * sizeof(int32_t));
+    t->off_tj_grad = place(&o, t->tj_grad.size() * sizeof(int32_t));
     t->bytes = o;
 }
 
 void BuildTables::pack(char *host) const
 {
-    std::memcpy(host, descs.data(), descs.size() * sizeof(PyrDescWrite));
-    for (int l = 1; l < LK_MAX_LEVELS; ++l)
-        if (!down[l].empty()) std::memcpy(host + off_down[l], down[l].data(), down[l].size() * sizeof(DownJob));
-    if (!grads.empty()) std::memcpy(host + off_grad, grads.data(), grads.size() * sizeof(GradJob));
+    auto put = [&](size_t off, const void *src, size_t bytes) { if (bytes) std::memcpy(host + off, src, bytes); };
+    put(0, descs.data(), descs.size() * sizeof(PyrDescWrite));
+    put(off_p12, p12.data(), p12.size() * sizeof(Pyr12Job));
+    for (int l = 1; l < LK_MAX_LEVELS; ++l) put(off_down[l], down[l].data(), down[l].size() * sizeof(DownJob));
+    put(off_grad, grads.data(), grads.size() * sizeof(GradJob));
+    put(off_tj_p12, tj_p12.data(), tj_p12.size() * sizeof(int32_t));
+    for (int l = 1; l < LK_MAX_LEVELS; ++l) put(off_tj_down[l], tj_down[l].data(), tj_down[l].size() * sizeof(int32_t));
+    put(off_tj_grad, tj_grad.data(), tj_grad.size() * sizeof(int32_t));
 }
 
 hipError_t launch_build_tables(const BuildTables &t, const char *d_base, hipStream_t s)
 {
     hipError_t e = launch_write_descs(reinterpret_cast<const PyrDescWrite *>(d_base), (int)t.descs.size(), s);
+    if (e == hipSuccess && !t.p12.empty())
+        e = launch_pyr12_batched(reinterpret_cast<const Pyr12Job *>(d_base + t.off_p12),
+                                 reinterpret_cast<const int32_t *>(d_base + t.off_tj_p12), (int)t.tj_p12.size(), s);
     for (int l = 1; l < LK_MAX_LEVELS && e == hipSuccess; ++l)
         if (!t.down[l].empty())
             e = launch_downsample_batched(reinterpret_cast<const DownJob *>(d_base + t.off_down[l]),
-                                          (int)t.down[l].size(), t.tiles_down[l], s);
+                                          reinterpret_cast<const int32_t *>(d_base + t.off_tj_down[l]),
+                                          (int)t.tj_down[l].size(), s);
     if (e == hipSuccess && !t.grads.empty())
-        e = launch_grad_batched(reinterpret_cast<const GradJob *>(d_base + t.off_grad), (int)t.grads.size(),
-                                t.tiles_grad, s);
+        e = launch_grad_batched(reinterpret_cast<const GradJob *>(d_base + t.off_grad),
+                                reinterpret_cast<const int32_t *>(d_base + t.off_tj_grad), (int)t.tj_grad.size(), s);
     return e;
 }
 

@@ -47,14 +47,17 @@ struct lk_pyramid {
 namespace lkmi {
 
 // Job tables of a batched pyramid build, laid out for one device buffer:
-// descriptor writes, down jobs level by level, then gradient jobs.
+// descriptor writes, fused level-1+2 jobs, down jobs level by level (levels
+// >= 3, or level 1 of two-level pyramids), gradient jobs, then one
+// tile-to-job table per launch.
 struct BuildTables {
     std::vector<PyrDescWrite> descs;
+    std::vector<Pyr12Job> p12;
     std::vector<DownJob> down[LK_MAX_LEVELS];
     std::vector<GradJob> grads;
-    int tiles_down[LK_MAX_LEVELS] = {0};
-    int tiles_grad = 0;
-    size_t off_down[LK_MAX_LEVELS] = {0}, off_grad = 0, bytes = 0;
+    std::vector<int32_t> tj_p12, tj_down[LK_MAX_LEVELS], tj_grad;
+    size_t off_p12 = 0, off_down[LK_MAX_LEVELS] = {0}, off_grad = 0;
+    size_t off_tj_p12 = 0, off_tj_down[LK_MAX_LEVELS] = {0}, off_tj_grad = 0, bytes = 0;
     void pack(char *host) const;
 };
 void make_build_tables(lk_pyramid *const *pyrs, int n, BuildTables *t);
@@ -72,5 +75,8 @@ TrackArgs make_args(const lk_params *p, int n, const float *pts, const float *gu
 lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
                      std::vector<BatchItem> *items, int *storage, long long *total);
 lk_result enqueue_build(lk_context *ctx, lk_pyramid *const *pyrs, int n, hipStream_t s);
-void pyramid_jobs(const lk_pyramid *p, std::vector<DownJob> *down_by_level, std::vector<GradJob> *grads);
+// Jobs of one pyramid build: levels 1+2 fused when the pyramid has three or
+// more levels, one down job per remaining level, gradient planes (binary16).
+void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<DownJob> *down_by_level,
+                  std::vector<GradJob> *grads);
 }  // namespace lkmi

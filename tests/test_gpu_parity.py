@@ -39,7 +39,8 @@ def gt(lk, ctx):
 
 # ------------------------------------------------------------------ pyramid
 
-@pytest.mark.parametrize("shape", [(480, 752), (121, 97), (64, 64), (33, 57), (1080, 1920)])
+@pytest.mark.parametrize("shape", [(480, 752), (121, 97), (64, 64), (33, 57), (1080, 1920), (13, 13), (29, 131),
+                                   (67, 65), (130, 258)])
 def test_pyramid_levels_f32(lk, ctx, gt, shape):
     import torch
     rng = np.random.default_rng(shape[0])
@@ -59,12 +60,12 @@ def test_pyramid_levels_f32(lk, ctx, gt, shape):
     lk.lk_pyramid_destroy(p)
 
 
-@pytest.mark.parametrize("shape", [(480, 752), (61, 83)])
-def test_pyramid_levels_and_gradients_f16(lk, ctx, gt, shape):
+@pytest.mark.parametrize("shape,levels", [((480, 752), 4), ((61, 83), 4), ((13, 27), 3), ((99, 257), 3),
+                                          ((600, 960), 5)])
+def test_pyramid_levels_and_gradients_f16(lk, ctx, gt, shape, levels):
     import torch
     rng = np.random.default_rng(7 + shape[1])
     img = rng.integers(0, 256, size=shape).astype(np.uint8)
-    levels = 4
     p, t = gt.pyramid(img, levels, lk.LK_STORAGE_F16)
     ref, rgx, rgy = oracle.pyramid(img.astype(np.float64), levels, f16=True)
     for l in range(1, levels):
