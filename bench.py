@@ -163,6 +163,44 @@ def time_steps(fn, steps, warmup):
     return wall, per
 
 
+def time_block(fn, reps, warmup):
+    """Mean duration of one call when `reps` calls run back to back, from two
+    HIP events on the launch stream around the whole run."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps * 1e-3
+
+
+def profiled_traffic(kernel, summary="profiles/hbm_counters_batched64.txt",
+                     source="paper_2607_01757_amd/csrc/lk_kernels.hip"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        lines = open(os.path.join(root, summary)).read().splitlines()
+        now = hashlib.sha256(open(os.path.join(root, source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    recorded = [l.split()[2] for l in lines if l.startswith("source sha256") and l.split()[3] == source]
+    if recorded != [now]:
+        return None
+    for l in lines:
+        f = l.split()
+        if len(f) == 3 and f[0] == "traffic" and f[1] == kernel:
+            return int(f[2])
+    return None
+
+
 def cpu_baseline(streams, n_sample, win, levels, fb):
     import oracle
     threads = os.cpu_count() or 1
@@ -205,8 +243,7 @@ def run_batched(args):
     # the tracker alone, same shape, for the roofline of the dominant kernel
     trk = lk.lk_batch_create(ctx, [], [], wl.pairs, wl.pts, None, wl.params, wl.out, wl.st, wl.res, None,
                              config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 1, 0))
-    _, trk_ms = time_steps(lambda: lk.lk_batch_run(trk), args.steps, args.warmup)
-    t_trk = float(np.mean(trk_ms)) * 1e-3
+    t_trk = time_block(lambda: lk.lk_batch_run(trk), max(args.steps, 10), args.warmup)
     _, pyr = time_steps(wl.build, args.steps, args.warmup)
     wall, per = time_steps(lambda: lk.lk_batch_run(step), args.steps, args.warmup)
     kps = wl.n * args.steps / wall
@@ -264,7 +301,8 @@ def run_batched(args):
         "tracked_fraction": float(np.mean(status == 0)),
         "roofline": {"bound": "alu", "kernel": "k_track_%s" % ("persist" if best.persistent else "batched"),
                      "achieved": f_alg / t_trk / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": f_alg / t_trk / 1e12 / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": f_alg / t_trk / 1e12 / PEAK_FP32_TFLOPS,
+                     "traffic": profiled_traffic("k_track_batched"),
                      "flops_per_launch": f_alg, "kernel_ms": t_trk * 1e3},
         "path_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": b_alg / step_s / 1e9,
                      "frac": b_alg / step_s / 1e9 / PEAK_HBM_GBS},
