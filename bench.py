@@ -51,15 +51,16 @@ def level_dims(w, h, levels):
     return out
 
 
-def footprint_bytes(pts, ends, w, h, levels, win, store_bytes):
+def footprint_bytes(pts, ends, w, h, levels, win, store_bytes, grad_bytes=0):
     """Unique bytes of the window footprints the tracker must read: template
-    windows (win+3)^2 around p / 2^l in the previous pyramid and target
+    windows (win+3)^2 around p / 2^l in the previous pyramid (plus its
+    gradient planes, grad_bytes per pixel, when they are stored) and target
     windows (win+1)^2 covering start and end in the next one."""
     hw = (win - 1) // 2
     total = 0
     for l, (lw, lh) in enumerate(level_dims(w, h, levels)):
-        s = 1 if l == 0 else store_bytes
         for pts_l, ext in ((pts / 2 ** l, hw + 2), (None, hw + 1)):
+            s = (1 if l == 0 else store_bytes) + (grad_bytes if pts_l is not None else 0)
             diff = np.zeros((lh + 1, lw + 1), np.int32)
             if pts_l is not None:
                 x0 = np.floor(pts_l[:, 0]) - ext + 1
@@ -222,7 +223,8 @@ def run_batched(args):
 
     streams = make_streams(args.streams, args.seed)
     ctx = lk.lk_context_create(0, 0)
-    wl = BatchedWorkload(lk, ctx, streams)
+    f16 = args.storage == "f16"
+    wl = BatchedWorkload(lk, ctx, streams, storage=lk.LK_STORAGE_F16 if f16 else lk.LK_STORAGE_F32)
     log("resident: %.1f MB of pyramids, %d keypoints" % (lk.lk_context_bytes_in_use(ctx) / 1e6, wl.n))
     # one untimed step with iteration counts (deterministic: same counts when timed)
     wl.step()
@@ -268,19 +270,32 @@ def run_batched(args):
             a.record(); wl.plain_frame(i); b.record()
             torch.cuda.synchronize()
             lat.append(a.elapsed_time(b))
+        # frames of one step arriving together: completion time of each
+        # frame when the plain path runs them one after another
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(streams) + 1)]
+        evs[0].record()
+        for i in range(len(streams)):
+            wl.plain_frame(i)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        done = [evs[0].elapsed_time(e) for e in evs[1:]]
         plain = {"value": wl.n * k / pw, "unit": "keypoints/s", "ms_per_step": pw / k * 1e3,
-                 "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99)}
+                 "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
+                 "step_completion_p50_ms": percentile(done, 50), "step_completion_p99_ms": percentile(done, 99)}
         log("plain: %.3f ms/step  %.3g kp/s" % (plain["ms_per_step"], plain["value"]))
 
     # algorithmic bytes of one step (whole path)
     b_frames = sum(s.width * s.height for s in streams)
-    b_levels = sum(4 * sum(w * h for (w, h) in level_dims(s.width, s.height, 3)[1:]) for s in streams)
+    esz = 2 if f16 else 4
+    b_levels = sum(esz * sum(w * h for (w, h) in level_dims(s.width, s.height, 3)[1:]) for s in streams)
+    if f16:   # binary16 gradient planes of every level (4 B per pixel)
+        b_levels += sum(4 * sum(w * h for (w, h) in level_dims(s.width, s.height, 3)) for s in streams)
     b_windows = 0
     off = 0
     for s in streams:
         c = len(s.pts)
         b_windows += footprint_bytes(s.pts.astype(np.float64), ends[off:off + c].astype(np.float64),
-                                     s.width, s.height, 3, 21, 4)
+                                     s.width, s.height, 3, 21, esz, 4 if f16 else 0)
         off += c
     b_io = wl.n * (8 + 8 + 1 + 4)
     b_alg = b_frames + b_levels + b_windows + b_io
@@ -290,9 +305,10 @@ def run_batched(args):
         "metric": "tracked keypoints/sec (batched, 64 streams) + p50/p99 frame latency",
         "value": kps, "unit": "keypoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f16" if f16 else "f32", "data": "synthetic",
         "config": {"workload": "batched: 64 streams, resolutions {640x480..1920x1080}, U[150,1500] keypoints, "
-                               "21x21 window, 3 levels, 30 iterations, eps 0.01, float32 storage; one step = "
+                               "21x21 window, 3 levels, 30 iterations, eps 0.01, %s storage; one step = " % (
+                                   "binary16" if f16 else "float32") +
                                "new-frame pyramids + all pairs in one graph-captured prepared batch",
                    "streams": len(streams), "keypoints_per_step": wl.n, "seed": args.seed,
                    "exec": {"persistent": best.persistent, "blocks_per_cu": best.blocks_per_cu,
@@ -302,7 +318,8 @@ def run_batched(args):
         "roofline": {"bound": "alu", "kernel": "k_track_%s" % ("persist" if best.persistent else "batched"),
                      "achieved": f_alg / t_trk / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": f_alg / t_trk / 1e12 / PEAK_FP32_TFLOPS,
-                     "traffic": profiled_traffic("k_track_batched"),
+                     # counters were taken for the float32-storage instantiation only
+                     "traffic": None if f16 else profiled_traffic("k_track_batched"),
                      "flops_per_launch": f_alg, "kernel_ms": t_trk * 1e3},
         "path_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": b_alg / step_s / 1e9,
                      "frac": b_alg / step_s / 1e9 / PEAK_HBM_GBS},
@@ -401,13 +418,12 @@ def run_stereo(args, f16):
         "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
         "batch2": {"value": kps_b, "p50_frame_ms": percentile(lat_b, 50), "p99_frame_ms": percentile(lat_b, 99)},
     }
-    if f16:
-        # precision of binary16 storage: the temporal pass of a few frames vs
-        # the FP64 oracle without storage rounding
+    if True:
+        # error of the temporal pass of a few frames vs the FP64 oracle
+        # (without storage rounding)
         import oracle
         errs = []
         for (t, p0) in inputs[:args.precision_frames]:
-            a = torch.empty(0)
             pa = lk.lk_pyramid_create(ctx, W, H, levels, storage)
             pb = lk.lk_pyramid_create(ctx, W, H, levels, storage)
             lk.lk_build_pyramid(ctx, pa, dl[t - 1])
@@ -421,11 +437,10 @@ def run_stereo(args, f16):
             errs.extend(np.abs(g_pts[ok] - r.pts[ok]).max(axis=1).tolist())
             lk.lk_pyramid_destroy(pa)
             lk.lk_pyramid_destroy(pb)
-            del a
         result["error_vs_fp64_oracle_px"] = {"max": float(np.max(errs)), "p99": float(np.percentile(errs, 99)),
                                              "points": len(errs), "frames": args.precision_frames}
-        log("binary16 storage vs FP64 oracle: max %.3g px p99 %.3g px over %d points" % (
-            np.max(errs), np.percentile(errs, 99), len(errs)))
+        log("%s storage vs FP64 oracle: max %.3g px p99 %.3g px over %d points" % (
+            "binary16" if f16 else "float32", np.max(errs), np.percentile(errs, 99), len(errs)))
     for p_ in pl + [pr]:
         lk.lk_pyramid_destroy(p_)
     lk.lk_context_destroy(ctx)
@@ -588,6 +603,51 @@ def run_serve(args):
     }
 
 
+def run_pair(args):
+    """Single pair: one 752x480 frame pair, 150 keypoints, 21x21, 3 levels,
+    float32 storage; one step = both pyramids + tracking, plain launches."""
+    import torch
+    import synth
+    import oracle
+    from paper_2607_01757_amd import lk
+
+    pr = synth.pair(args.seed, 752, 480, 150, 8.0, 2.0)
+    ctx = lk.lk_context_create(0, 0)
+    a = torch.from_numpy(pr.prev).cuda()
+    b = torch.from_numpy(pr.next).cuda()
+    pa = lk.lk_pyramid_create(ctx, 752, 480, 3, lk.LK_STORAGE_F32)
+    pb = lk.lk_pyramid_create(ctx, 752, 480, 3, lk.LK_STORAGE_F32)
+    pts = torch.from_numpy(pr.pts).cuda()
+    prm = lk.make_params(21, 3, 30, 0.01, 1e-6, 0.0)
+    out, st, res, _ = lk.outputs(150, 3)
+
+    def step():
+        lk.lk_build_pyramid(ctx, pa, a)
+        lk.lk_build_pyramid(ctx, pb, b)
+        lk.lk_track(ctx, pa, pb, pts, None, 150, prm, out, st, res, None)
+    wall, per = time_steps(step, args.steps, args.warmup)
+    g_pts, g_st = out.cpu().numpy(), st.cpu().numpy()
+    r = oracle.track(pr.prev, pr.next, pr.pts, win=21, levels=3, min_eig=1e-6, nthreads=os.cpu_count() or 1)
+    ok = (g_st == 0) & (r.status == 0)
+    err = np.abs(g_pts[ok] - r.pts[ok]).max(axis=1)
+    result = {
+        "metric": "tracked keypoints/sec + p50/p99 frame latency (single pair, plain per-frame)",
+        "value": 150 * args.steps / wall, "unit": "keypoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "single pair 752x480, 150 keypoints, 21x21, 3 levels, 30 iterations, eps 0.01, "
+                               "float32 storage; step = both pyramids + tracking"},
+        "p50_frame_ms": percentile(per, 50), "p99_frame_ms": percentile(per, 99),
+        "error_vs_fp64_oracle_px": {"max": float(err.max()), "p99": float(np.percentile(err, 99)),
+                                    "points": int(ok.sum())},
+        "status_agreement": float(np.mean(g_st == r.status)),
+    }
+    lk.lk_pyramid_destroy(pa)
+    lk.lk_pyramid_destroy(pb)
+    lk.lk_context_destroy(ctx)
+    return result
+
+
 def run_detect(args):
     """Shi-Tomasi detection over the next frames of the 64-stream batch: a
     fresh detection (no occupied points) and a top-up that keeps new corners
@@ -678,8 +738,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="batched", choices=["batched", "stereo", "stereo16", "serve", "detect",
-                                                           "copy"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "pair", "stereo", "stereo16", "serve",
+                                                           "detect", "copy"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--precision-frames", type=int, default=5)
     ap.add_argument("--serve-streams", type=int, default=256)
@@ -692,6 +752,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--gftt-corners", type=int, default=200)
+    ap.add_argument("--storage", choices=["f32", "f16"], default="f32",
+                    help="pyramid storage of the batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (streams would be sharded "
@@ -703,6 +765,8 @@ def main():
         res = run_serve(args)
     elif args.workload == "detect":
         res = run_detect(args)
+    elif args.workload == "pair":
+        res = run_pair(args)
     elif args.workload in ("stereo", "stereo16"):
         res = run_stereo(args, args.workload == "stereo16")
     else:
