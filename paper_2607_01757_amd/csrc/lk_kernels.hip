@@ -528,9 +528,20 @@ struct Geo {
     static constexpr int EXY = ((WMAX + R - 1) / R) * R;
     static constexpr int TW = EXX + 1, TH = EXY + 1;           // bilinear taps
     static constexpr int SW = TW + 2, SH = TH + 2;             // taps plus the Scharr halo
-    static constexpr int LDS = SW * SH + 2 * TW * TH;          // staged level + two gradient planes, floats per wave
     // column walk of the gradient build: lanes are tap columns, GROUPS row
     // groups side by side, RPG tap rows each
+    static constexpr int TBW = EXX + 2, TBH = EXY + 2;         // interpolated template incl. a one-pixel halo
+    // LDS row strides of the tap region and of the interpolated template,
+    // chosen so that the lane segments of a wavefront (rows r0 = 0, R, 2R)
+    // fall on disjoint banks whether the LDS has 32 or 64 banks: for 7-row
+    // segments 7 x 67 = 21 (mod 64), for 16-row segments 16 x 34 = 32 (mod 64)
+    static constexpr int RS = CW == 1 && R == 7 ? 67 : (CW == 1 && R == 16 ? 34 : (TW | 1));
+    static constexpr int TBS = RS > TBW ? RS : (TBW | 1);
+    static constexpr int LDS_OLD = SW * SH + 2 * TW * TH;      // staged level + two gradient planes
+    static constexpr int LDS_FAST = SW * SH + TBS * TBH;       // staged level + interpolated template
+    static constexpr int LDS_REG = RS * TH;                    // target tap region
+    static constexpr int LDS = LDS_OLD > LDS_FAST ? (LDS_OLD > LDS_REG ? LDS_OLD : LDS_REG)
+                                                  : (LDS_FAST > LDS_REG ? LDS_FAST : LDS_REG);   // floats per wave
     static constexpr int CPASS = (TW + 63) / 64;
     static constexpr int GROUPS = TW <= 64 ? 64 / TW : 1;
     static constexpr int RPG = (TH + GROUPS - 1) / GROUPS;
@@ -736,6 +747,160 @@ __device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, bool i
     }
 }
 
+// One element of a plane at byte offset voff + soff (soff: a wave-uniform
+// offset that the load takes from a scalar register).
+template <int KIND>
+__device__ __forceinline__ float bload_at(const Plane &p, int voff, int soff)
+{
+    if constexpr (KIND == K_U8) return (float)__builtin_amdgcn_raw_buffer_load_b8(p.rs, voff, soff, 0);
+    else if constexpr (KIND == K_F16)
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(p.rs, voff, soff, 0)));
+    else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs, voff, soff, 0));
+}
+
+// The rectangle [x0, x0 + RW) x [y0, y0 + RH) of a level into wave-private
+// LDS, dense with row stride RW.  Lanes are (row group, column): each load
+// instruction fills rows of the rectangle, its row offset a scalar.  Lanes
+// beyond the groups and rows beyond the rectangle repeat an element another
+// lane writes (same address, same value), so no load is predicated and the
+// loads of a lane issue back to back.  With `inside` (wave-uniform) every
+// position is in the level; otherwise positions are clamped to it (bilinear
+// taps replicate the edges).
+template <int KIND, int RW, int RH, int DS = RW>
+__device__ __forceinline__ void load_rect(const Plane &P, int x0, int y0, bool inside, int lane, float *dst)
+{
+    constexpr int es = KIND == K_U8 ? 1 : (KIND == K_F16 ? 2 : 4);
+    constexpr int NG = RW <= 64 ? 64 / RW : 1;          // row groups side by side
+    constexpr int CP = RW <= 64 ? 1 : (RW + 63) / 64;   // column passes
+    constexpr int KS = (RH + NG - 1) / NG;
+    constexpr bool RAGGED = KS * NG != RH;                // the last step has rows past the end
+#pragma unroll
+    for (int cp = 0; cp < CP; ++cp) {
+        int g, c;
+        if constexpr (RW <= 64) {
+            g = lane / RW;
+            c = lane - g * RW;
+            if (g >= NG) { g = 0; }                       // idle lanes repeat group 0
+        } else {
+            g = 0;
+            c = min(lane + 64 * cp, RW - 1);              // the last pass repeats the last column
+        }
+        // steps of KB rows per group, unrolled within a step (bounds the
+        // registers the loads in flight take on large windows)
+        constexpr int KB = KS <= 12 ? KS : 8;
+        if (inside) {
+            const int voff = ((y0 + g) * P.pitch + x0 + c) * es;
+#pragma unroll 1
+            for (int k0 = 0; k0 < KS; k0 += KB) {
+                float *d = dst + (g + NG * k0) * DS + c;
+                const int so = k0 * NG * P.pitch * es;
+#pragma unroll
+                for (int kk = 0; kk < KB; ++kk) {
+                    const int k = k0 + kk;
+                    if (k >= KS) break;
+                    if (RAGGED && k == KS - 1) {
+                        const int r = min(g + NG * k, RH - 1);
+                        dst[r * DS + c] = bload_at<KIND>(P, ((y0 + r) * P.pitch + x0 + c) * es, 0);
+                    } else {
+                        d[kk * NG * DS] = bload_at<KIND>(P, voff, so + kk * NG * P.pitch * es);
+                    }
+                }
+            }
+        } else {
+            const int xs = clampi(x0 + c, 0, P.w - 1);
+#pragma unroll 1
+            for (int k0 = 0; k0 < KS; k0 += KB) {
+#pragma unroll
+                for (int kk = 0; kk < KB; ++kk) {
+                    const int k = k0 + kk;
+                    if (k >= KS) break;
+                    const int r = RAGGED && k == KS - 1 ? min(g + NG * k, RH - 1) : g + NG * k;
+                    const int ys = clampi(y0 + r, 0, P.h - 1);
+                    dst[r * DS + c] = bload_at<KIND>(P, (ys * P.pitch + xs) * es, 0);
+                }
+            }
+        }
+    }
+}
+
+// Template of a window whose staged region lies inside the level (one
+// column per lane).  The level region E is staged, the template is sampled
+// bilinearly once on the (win+2)^2 grid of window positions plus a one-pixel
+// halo (Tb), and each lane takes T and the Scharr gradients of its strip
+// from Tb.  In exact arithmetic this equals sampling the Scharr planes of
+// the level bilinearly (both are linear filters with the same weights at
+// every window position); only the rounding order differs.
+template <class G, int KIND>
+__device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_lo, const Weights &w,
+                                              const LaneCfg &lc, int win, int lane, float *lds,
+                                              float (&T)[G::R][G::CW], float (&GX)[G::R][G::CW],
+                                              float (&GY)[G::R][G::CW])
+{
+    static_assert(G::CW == 1, "one window column per lane");
+    constexpr int R = G::R, SW = G::SW, SH = G::SH, TBW = G::TBW, TBH = G::TBH, TBS = G::TBS;
+    float *E = lds, *Tb = lds + SW * SH;
+    load_rect<KIND, SW, SH>(P, tx_lo, ty_lo, true, lane, E);
+    wave_lds_sync();
+    {
+        // lanes beyond the groups, and rows past the grid, repeat an entry
+        // another lane writes (same value), so nothing is predicated
+        constexpr int NG = 64 / TBW, KS = (TBH + NG - 1) / NG;
+        constexpr bool RAGGED = KS * NG != TBH;
+        int g = lane / TBW;
+        const int b = lane - g * TBW;
+        if (g >= NG) g = 0;
+        constexpr int KB = KS <= 12 ? KS : 8;
+#pragma unroll 1
+        for (int k0 = 0; k0 < KS; k0 += KB) {
+            const float *e = E + (g + NG * k0) * SW + b;
+            float *t = Tb + (g + NG * k0) * TBS + b;
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk) {
+                const int k = k0 + kk;
+                if (k >= KS) break;
+                if (RAGGED && k == KS - 1) {
+                    const int a2 = min(g + NG * k, TBH - 1);
+                    const float *q = E + a2 * SW + b;
+                    Tb[a2 * TBS + b] = bilerp(w, q[0], q[1], q[SW], q[SW + 1]);
+                } else {
+                    const float *q = e + kk * NG * SW;
+                    t[kk * NG * TBS] = bilerp(w, q[0], q[1], q[SW], q[SW + 1]);
+                }
+            }
+        }
+    }
+    wave_lds_sync();
+    // the lane's strip: rows a = 0 .. R+1 of Tb around its column, with a
+    // three-row sliding window of D = right - left and S = (3 l + 10 c + 3 r) / 32
+    const float *tb = Tb + lc.r0 * TBS + lc.c0;
+    float d0 = 0.0f, d1 = 0.0f, s0 = 0.0f, s1 = 0.0f, c1 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < R + 2; ++a) {
+        const float l = tb[a * TBS], c = tb[a * TBS + 1], r = tb[a * TBS + 2];
+        const float d2 = r - l, s2 = fmaf(0.09375f, l + r, 0.3125f * c);
+        if (a >= 2) {
+            const int i = a - 2;
+            const bool ok = c_valid(lc, win, i, 0);
+            T[i][0] = ok ? c1 : 0.0f;
+            GX[i][0] = ok ? fmaf(0.3125f, d1, 0.09375f * (d0 + d2)) : 0.0f;
+            GY[i][0] = ok ? s2 - s0 : 0.0f;
+        }
+        d0 = d1; d1 = d2; s0 = s1; s1 = s2; c1 = c;
+    }
+}
+
+// Taps of this lane from a target region loaded by load_rect at the lane's
+// window origin (region row stride G::RS).
+template <class G>
+__device__ __forceinline__ void region_taps(const float *region, const LaneCfg &lc, float (&t)[G::R + 1][G::CW + 1])
+{
+    const float *q = region + lc.r0 * G::RS + lc.c0;
+#pragma unroll
+    for (int i = 0; i <= G::R; ++i)
+#pragma unroll
+        for (int j = 0; j <= G::CW; ++j) t[i][j] = q[i * G::RS + j];
+}
+
 struct PassResult {
     int status;
     float ox, oy;      // end point, level-0 pixels
@@ -769,16 +934,32 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         const LevelDesc LJ = uniform_level(J.lv[l]);
         const float cxs = ldexpf(px, -l), cys = ldexpf(py, -l);   // exact scaling
         const float flx = floorf(cxs), fly = floorf(cys);
-        cix = (int)flx; ciy = (int)fly;
+        cix = uniform_i((int)flx); ciy = uniform_i((int)fly);
         cfx = cxs - flx; cfy = cys - fly;                         // exact
         // ---- template T, Gx, Gy on the window around c = p / 2^l
         {
             const int tx_lo = cix - h - 1, ty_lo = ciy - h - 1;
-            if (l == 0) stage_taps<G, K_U8, ST == LK_STORAGE_F16>(LI, tx_lo, ty_lo, lane, lds);
-            else if constexpr (ST == LK_STORAGE_F16) stage_taps<G, K_F16, true>(LI, tx_lo, ty_lo, lane, lds);
-            else stage_taps<G, K_F32, false>(LI, tx_lo, ty_lo, lane, lds);
-            lane_template<G>(lds, lc, win, bilinear_weights(cfx, cfy), cix - h + lc.c0, ciy - h + lc.r0,
-                             cix - h, ciy - h, LI.w, LI.h, T, GX, GY);
+            wave_lds_sync();          // the previous level's reads of this LDS are done
+            bool fast = false;
+            if constexpr (ST == LK_STORAGE_F32 && G::CW == 1)
+                fast = tx_lo >= 0 && ty_lo >= 0 && tx_lo + G::SW <= LI.w && ty_lo + G::SH <= LI.h;
+            if (fast) {
+                if constexpr (ST == LK_STORAGE_F32 && G::CW == 1) {
+                    const Weights wt = bilinear_weights(cfx, cfy);
+                    if (l == 0)
+                        fast_template<G, K_U8>(make_plane<K_U8>(LI.img, LI.pitch, LI.w, LI.h), tx_lo, ty_lo, wt, lc,
+                                               win, lane, lds, T, GX, GY);
+                    else
+                        fast_template<G, K_F32>(make_plane<K_F32>(LI.img, LI.pitch, LI.w, LI.h), tx_lo, ty_lo, wt,
+                                                lc, win, lane, lds, T, GX, GY);
+                }
+            } else {
+                if (l == 0) stage_taps<G, K_U8, ST == LK_STORAGE_F16>(LI, tx_lo, ty_lo, lane, lds);
+                else if constexpr (ST == LK_STORAGE_F16) stage_taps<G, K_F16, true>(LI, tx_lo, ty_lo, lane, lds);
+                else stage_taps<G, K_F32, false>(LI, tx_lo, ty_lo, lane, lds);
+                lane_template<G>(lds, lc, win, bilinear_weights(cfx, cfy), cix - h + lc.c0, ciy - h + lc.r0,
+                                 cix - h, ciy - h, LI.w, LI.h, T, GX, GY);
+            }
         }
         float sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
 #pragma unroll
@@ -826,7 +1007,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
                 return pr;
             }
             const float fux = floorf(ux), fuy = floorf(uy);
-            const int bx = cix + (int)fux, by = ciy + (int)fuy;
+            const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
             if (bx != jbx || by != jby) {
                 const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
                 if (l == 0) load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
@@ -871,7 +1052,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         // near the frame before converting (taps are clamped anyway)
         const float fux = fminf(fmaxf(floorf(ux), (float)(-cix - h - 2)), (float)(LJ.w + h + 2 - cix));
         const float fuy = fminf(fmaxf(floorf(uy), (float)(-ciy - h - 2)), (float)(LJ.h + h + 2 - ciy));
-        const int bx = cix + (int)fux, by = ciy + (int)fuy;
+        const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
         const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
         load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
         const Weights w = bilinear_weights(ux - fux, uy - fuy);
