@@ -283,27 +283,43 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
         }
     }
     __syncthreads();
-    // 2. level-1 region by column walk: thread = (column, group of rows);
-    //    the horizontal sums of level-0 rows slide down with the outputs
+    // 2. level-1 region by column walk: thread = (pair of columns, group of
+    //    rows); the horizontal sums of level-0 rows slide down with the
+    //    outputs.  The 7 taps of a column pair come from 3 aligned dwords.
     {
-        constexpr int G = kThreads / kP1W;                       // 3 row groups
-        constexpr int RPG = (kP1H + G - 1) / G;                  // 12 rows each
-        const int c = threadIdx.x % kP1W, g = threadIdx.x / kP1W;
+        constexpr int NP = (kP1W + 1) / 2;                       // 34 column pairs (column 67 is padding)
+        constexpr int G = kThreads / NP;                         // 7 row groups
+        constexpr int RPG = (kP1H + G - 1) / G;                  // 5 rows each
+        const int pr = threadIdx.x % NP, g = threadIdx.x / NP;
         if (g < G) {
+            const int c = 2 * pr;
             const int r_lo = g * RPG, r_hi = min(kP1H, r_lo + RPG);
-            // level-1 x1 = rx1 + c has its centre tap at level-0 x = 2 x1,
-            // staged column 2 x1 - a0 = 2 c + 12
-            const uint8_t *col = &sm.in[0][2 * c + 10];
-            auto hsum = [&](int row) {
-                const uint8_t *q = col + row * kP0W;
-                return binom5((float)q[0], (float)q[1], (float)q[2], (float)q[3], (float)q[4]);
+            // level-1 x1 = rx1 + c has its centre tap at staged column 2 c + 12:
+            // taps of columns c and c + 1 are staged bytes 2c+10 .. 2c+16, inside
+            // the dwords at bytes [2c+8, 2c+20) (4-byte aligned: c is even)
+            const uint32_t *col = reinterpret_cast<const uint32_t *>(&sm.in[0][2 * c + 8]);
+            auto byte_f = [](uint32_t w, int k) { return (float)((w >> (8 * k)) & 0xFFu); };
+            auto hsum2 = [&](int row, float &a, float &b) {
+                const uint32_t *q = col + row * (kP0W / 4);
+                const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
+                const float t2 = byte_f(w0, 2), t3 = byte_f(w0, 3), t4 = byte_f(w1, 0), t5 = byte_f(w1, 1);
+                const float t6 = byte_f(w1, 2), t7 = byte_f(w1, 3), t8 = byte_f(w2, 0);
+                a = binom5(t2, t3, t4, t5, t6);
+                b = binom5(t4, t5, t6, t7, t8);
             };
             // output row r uses level-0 staged rows 2 r .. 2 r + 4
-            float h0 = hsum(2 * r_lo), h1 = hsum(2 * r_lo + 1), h2 = hsum(2 * r_lo + 2);
+            float a0, b0, a1, b1, a2, b2;
+            hsum2(2 * r_lo, a0, b0);
+            hsum2(2 * r_lo + 1, a1, b1);
+            hsum2(2 * r_lo + 2, a2, b2);
             for (int r = r_lo; r < r_hi; ++r) {
-                const float h3 = hsum(2 * r + 3), h4 = hsum(2 * r + 4);
-                sm.l1[r][c] = to_storage(binom5(h0, h1, h2, h3, h4), f16);
-                h0 = h2; h1 = h3; h2 = h4;
+                float a3, b3, a4, b4;
+                hsum2(2 * r + 3, a3, b3);
+                hsum2(2 * r + 4, a4, b4);
+                sm.l1[r][c] = to_storage(binom5(a0, a1, a2, a3, a4), f16);
+                sm.l1[r][c + 1] = to_storage(binom5(b0, b1, b2, b3, b4), f16);
+                a0 = a2; a1 = a3; a2 = a4;
+                b0 = b2; b1 = b3; b2 = b4;
             }
         }
     }
