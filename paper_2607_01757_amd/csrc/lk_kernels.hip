@@ -420,32 +420,78 @@ __global__ __launch_bounds__(kThreads) void k_pyr12_batched(const Pyr12Job *jobs
 
 // ------------------------------------------------------ binary16 gradient planes
 
-struct GradSmem {
-    float s[kGradTileH + 2][kGradTileW + 3];
+// Staged window of a gradient tile: rows y0-1 .. y0+TH, columns from x0-16
+// (16-byte aligned for both 8-bit and binary16 sources), as floats.
+constexpr int kGradSW = kGradTileW + 32;
+
+struct alignas(16) GradSmem {
+    float s[kGradTileH + 2][kGradSW];
 };
 
 template <int SK>
 __device__ void grad_tile(const GradJob &j, int tile, GradSmem &sm)
 {
+    constexpr int es = SK == K_U8 ? 1 : 2;
+    constexpr int PX = 16 / es;                          // pixels per 16-byte chunk
+    constexpr int NCH = kGradSW / PX;                     // chunks per staged row
     auto &s = sm.s;
     const int tx = tile % j.tiles_x, ty = tile / j.tiles_x;
     const int x0 = tx * kGradTileW, y0 = ty * kGradTileH;
-    for (int i = threadIdx.x; i < (kGradTileH + 2) * (kGradTileW + 2); i += kThreads) {
-        const int r = i / (kGradTileW + 2), c = i - r * (kGradTileW + 2);
+    const int a0 = x0 - 16;                               // staged column 0
+    const bool vec_ok = ((j.spitch * es) & 15) == 0 && (reinterpret_cast<uintptr_t>(j.src) & 15) == 0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(j.src), (short)0, j.spitch * j.h * es, kBufWord3);
+    // 1. rows y0-1 .. y0+TH (reflect-101 into the level), columns a0 .. a0+SW;
+    //    16-byte loads for chunks inside the level, per pixel (reflected) at its edges
+    for (int i = threadIdx.x; i < (kGradTileH + 2) * NCH; i += kThreads) {
+        const int r = i / NCH, c = i - r * NCH;
         const int gy = reflect101(min(y0 - 1 + r, j.h), j.h);
-        const int gx = reflect101(min(x0 - 1 + c, j.w), j.w);
-        s[r][c] = ldpx<SK>(j.src, gy * j.spitch + gx);
+        const int xs = a0 + c * PX;
+        float *dst = &s[r][c * PX];
+        if (vec_ok && xs >= 0 && xs + PX <= j.w) {
+            const uint4 v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (gy * j.spitch + xs) * es, 0, 0));
+            unpack_chunk<SK>(v, dst);
+        } else {
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int gx = reflect101(clampi(xs + k, -1, j.w), j.w);
+                dst[k] = ldpx<SK>(j.src, gy * j.spitch + gx);
+            }
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kGradTileH * kGradTileW; i += kThreads) {
-        const int r = i / kGradTileW, c = i - r * kGradTileW;
+    // 2. each thread: 4 consecutive pixels of one row (staged columns
+    //    16 + c - 1 .. 16 + c + 4 of rows r .. r + 2)
+    {
+        const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 4;
         const int x = x0 + c, y = y0 + r;
-        if (x < j.w && y < j.h) {
-            const float gx = (3.0f * (s[r][c + 2] - s[r][c]) + 10.0f * (s[r + 1][c + 2] - s[r + 1][c])
-                              + 3.0f * (s[r + 2][c + 2] - s[r + 2][c])) * 0.03125f;
-            const float gy = (3.0f * (s[r + 2][c] - s[r][c]) + 10.0f * (s[r + 2][c + 1] - s[r][c + 1])
-                              + 3.0f * (s[r + 2][c + 2] - s[r][c + 2])) * 0.03125f;
-            j.dst[y * j.dpitch + x] = __floats2half2_rn(gx, gy);
+        if (y < j.h) {
+            float t[3][6];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) t[a][k] = s[r + a][15 + c + k];
+            __half2 g[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float gx = (3.0f * (t[0][k + 2] - t[0][k]) + 10.0f * (t[1][k + 2] - t[1][k])
+                                  + 3.0f * (t[2][k + 2] - t[2][k])) * 0.03125f;
+                const float gy = (3.0f * (t[2][k] - t[0][k]) + 10.0f * (t[2][k + 1] - t[0][k + 1])
+                                  + 3.0f * (t[2][k + 2] - t[0][k + 2])) * 0.03125f;
+                g[k] = __floats2half2_rn(gx, gy);
+            }
+            if (x + 3 < j.w) {
+                uint4 u;
+                u.x = __builtin_bit_cast(uint32_t, g[0]);
+                u.y = __builtin_bit_cast(uint32_t, g[1]);
+                u.z = __builtin_bit_cast(uint32_t, g[2]);
+                u.w = __builtin_bit_cast(uint32_t, g[3]);
+                *reinterpret_cast<uint4 *>(j.dst + (size_t)y * j.dpitch + x) = u;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (x + k < j.w) j.dst[(size_t)y * j.dpitch + x + k] = g[k];
+            }
         }
     }
 }
