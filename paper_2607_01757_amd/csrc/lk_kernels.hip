@@ -52,19 +52,20 @@ __device__ __forceinline__ float uniform_f(float v)
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Sum over the 64 lanes of a wavefront.  Every lane returns the same value:
-// each step adds a lane's value to its partner's with the operands swapped,
-// and float addition is commutative.
+// Sum over the 64 lanes of a wavefront, in one fixed order: pairs, quads,
+// 8-lane halves and 16-lane rows by DPP, then row 0 + row 1 into row 1 and
+// row 2 + row 3 into row 3 (row broadcast of lane 15), then rows 0-1 into
+// rows 2-3 (row broadcast of lane 31); lane 63 then holds the total, which is
+// read into a scalar register, so every lane gets the same bits.
 __device__ __forceinline__ float wave_sum(float v)
 {
     v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
     v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
     v += dpp_move<0x141>(v);   // row_half_mirror: quad <-> quad within 8 lanes
     v += dpp_move<0x140>(v);   // row_mirror: half-row <-> half-row within 16 lanes
-    v += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));  // lane ^ 16
-    float lo = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
-    float hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
-    return lo + hi;
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 // Pixel loads by element kind.
@@ -943,7 +944,7 @@ __device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_
         if (a >= 2) {
             const int i = a - 2;
             const bool ok = c_valid(lc, win, i, 0);
-            T[i][0] = ok ? c1 : 0.0f;
+            T[i][0] = c1;                  // invalid pixels have GX = GY = 0: they add nothing
             GX[i][0] = ok ? fmaf(0.3125f, d1, 0.09375f * (d0 + d2)) : 0.0f;
             GY[i][0] = ok ? s2 - s0 : 0.0f;
         }
