@@ -127,6 +127,16 @@ class BatchedWorkload:
     def build(self):
         self.lk.lk_build_pyramids(self.ctx, self.next_pyr, self.next_img)
 
+    def time_build(self, reps, warmup):
+        """Device time of the new-frame pyramids of every stream: a prepared,
+        graph-captured batch with no pairs, replayed back to back."""
+        lk = self.lk
+        b = lk.lk_batch_create(self.ctx, self.next_pyr, self.next_img, [], self.pts, None, self.params, self.out,
+                               self.st, self.res, None, config=lk.lk_exec_config(0, 0, 1, 0))
+        t = time_block(lambda: lk.lk_batch_run(b), reps, warmup)
+        lk.lk_batch_destroy(b)
+        return t
+
     def track(self, iters=False):
         self.lk.lk_track_batched(self.ctx, self.pairs, self.pts, None, self.params, self.out, self.st,
                                  self.res, self.it if iters else None)
@@ -246,11 +256,11 @@ def run_batched(args):
     trk = lk.lk_batch_create(ctx, [], [], wl.pairs, wl.pts, None, wl.params, wl.out, wl.st, wl.res, None,
                              config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 1, 0))
     t_trk = time_block(lambda: lk.lk_batch_run(trk), max(args.steps, 10), args.warmup)
-    _, pyr = time_steps(wl.build, args.steps, args.warmup)
+    t_pyr = wl.time_build(max(args.steps, 10), args.warmup)
     wall, per = time_steps(lambda: lk.lk_batch_run(step), args.steps, args.warmup)
     kps = wl.n * args.steps / wall
     log("batched (graph): %.3f ms/step  %.3g kp/s  tracker %.3f ms  pyramids %.3f ms" %
-        (wall / args.steps * 1e3, kps, t_trk * 1e3, np.mean(pyr)))
+        (wall / args.steps * 1e3, kps, t_trk * 1e3, t_pyr * 1e3))
     # the same step through the unprepared batched calls (tables shipped per call)
     uw, _ = time_steps(wl.step, args.steps, args.warmup)
     unprepared = {"value": wl.n * args.steps / uw, "unit": "keypoints/s", "ms_per_step": uw / args.steps * 1e3}
@@ -323,7 +333,7 @@ def run_batched(args):
                      "flops_per_launch": f_alg, "kernel_ms": t_trk * 1e3},
         "path_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": b_alg / step_s / 1e9,
                      "frac": b_alg / step_s / 1e9 / PEAK_HBM_GBS},
-        "pyramid_ms": float(np.mean(pyr)),
+        "pyramid_ms": t_pyr * 1e3,
         "unprepared_batched": unprepared,
         "plain": plain,
     }
@@ -721,6 +731,93 @@ def run_detect(args):
     return result
 
 
+SWEEP_KP = (160, 192, 256, 384, 512, 768, 1000, 1500)
+
+
+def run_sweep(args):
+    """Tracker cost against the keypoint budget per frame and the frame size
+    (the paper's keypoint-count ablation and its observation that front-end
+    time grows with the pixel count; Sec. IV).  For every resolution of the
+    batched workload and every budget: 64 streams of that shape in one tuned,
+    graph-captured step (pyramids + tracking), the tracker alone, and one
+    frame alone through the plain per-frame calls."""
+    import torch
+    import synth
+    from paper_2607_01757_amd import lk
+
+    ctx = lk.lk_context_create(0, 0)
+    n_str = args.streams
+    distinct = min(n_str, 8)          # distinct frame pairs per resolution, repeated over the streams
+    reps = max(args.steps, 10)
+    rows = []
+    for (w, h) in synth.RESOLUTIONS:
+        t0 = time.time()
+        base = [synth.pair(args.seed * 1000 + s, w, h, max(SWEEP_KP)) for s in range(distinct)]
+        streams = [base[s % distinct] for s in range(n_str)]
+        wl = BatchedWorkload(lk, ctx, streams)
+        t_pyr = wl.time_build(reps, args.warmup)
+        log("%dx%d: %d streams ready in %.1fs, pyramids %.3f ms" % (w, h, n_str, time.time() - t0, t_pyr * 1e3))
+        for kp in SWEEP_KP:
+            n = kp * n_str
+            pts = torch.from_numpy(np.concatenate([s.pts[:kp] for s in streams])).cuda()
+            pairs = [(a, b, i * kp, kp) for i, (a, b) in enumerate(zip(wl.prev_pyr, wl.next_pyr))]
+            out, st, res, _ = lk.outputs(n, 3)
+            step = lk.lk_batch_create(ctx, wl.next_pyr, wl.next_img, pairs, pts, None, wl.params, out, st, res,
+                                      None, config=lk.lk_exec_config(0, 4, 1, 0))
+            best, _ = lk.lk_batch_tune(step, reps=3)
+            trk = lk.lk_batch_create(ctx, [], [], pairs, pts, None, wl.params, out, st, res, None,
+                                     config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 1, 0))
+            t_trk = time_block(lambda: lk.lk_batch_run(trk), reps, args.warmup)
+            t_step = time_block(lambda: lk.lk_batch_run(step), reps, args.warmup)
+
+            def plain():
+                lk.lk_build_pyramid(ctx, wl.next_pyr[0], wl.next_img[0])
+                lk.lk_track(ctx, wl.prev_pyr[0], wl.next_pyr[0], pts[:kp], None, kp, wl.params, out[:kp],
+                            st[:kp], res[:kp], None)
+            t_plain = time_block(plain, reps, args.warmup)
+            lat = []
+            for _ in range(reps):       # one frame alone: events around it, idle GPU before
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(); plain(); b.record()
+                torch.cuda.synchronize()
+                lat.append(a.elapsed_time(b))
+            ok = float((st == 0).float().mean().item())
+            rows.append({"width": w, "height": h, "kp_per_frame": kp, "streams": n_str, "keypoints": n,
+                         "step_ms": t_step * 1e3, "tracker_ms": t_trk * 1e3, "pyramid_ms": t_pyr * 1e3,
+                         "kp_per_s": n / t_step, "tracker_kp_per_s": n / t_trk,
+                         "tracker_ns_per_kp": t_trk / n * 1e9, "plain_frame_ms": t_plain * 1e3,
+                         "plain_frame_latency_p50_ms": percentile(lat, 50),
+                         "exec": [best.persistent, best.blocks_per_cu], "tracked_fraction": ok})
+            log("  %4d kp/frame: step %.3f ms (%.3g kp/s), tracker %.3f ms (%.2f ns/kp), plain frame %.3f ms "
+                "back to back, %.3f ms alone" % (kp, t_step * 1e3, n / t_step, t_trk * 1e3, t_trk / n * 1e9,
+                                                 t_plain * 1e3, percentile(lat, 50)))
+            lk.lk_batch_destroy(step)
+            lk.lk_batch_destroy(trk)
+            del pts, out, st, res
+        wl.close()
+        del wl
+        torch.cuda.synchronize()
+    # normalised to the 256-keypoint budget at each resolution (the paper's
+    # presentation of its ablation)
+    ref = {(r["width"], r["height"]): r for r in rows if r["kp_per_frame"] == 256}
+    for r in rows:
+        b = ref[(r["width"], r["height"])]
+        r["plain_frame_rel_256"] = r["plain_frame_latency_p50_ms"] / b["plain_frame_latency_p50_ms"]
+        r["step_rel_256"] = r["step_ms"] / b["step_ms"]
+    big = max(rows, key=lambda r: (r["width"] * r["height"], r["kp_per_frame"]))
+    lk.lk_context_destroy(ctx)
+    return {
+        "metric": "tracked keypoints/sec against keypoints per frame and frame size (batched, 64 streams)",
+        "value": big["kp_per_s"], "unit": "keypoints/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": big["step_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "sweep: %d streams of one resolution in {640x480..1920x1080} x keypoints per "
+                               "frame in %s; 21x21, 3 levels, 30 iterations, eps 0.01, float32 storage; value = "
+                               "the 1920x1080, %d-keypoint point" % (n_str, list(SWEEP_KP), max(SWEEP_KP))},
+        "rows": rows,
+    }
+
+
 def run_copy(args):
     """Plain device copy of a known size (calibrates rocprof byte counters)."""
     import torch
@@ -739,7 +836,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "pair", "stereo", "stereo16", "serve",
-                                                           "detect", "copy"])
+                                                           "detect", "sweep", "copy"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--precision-frames", type=int, default=5)
     ap.add_argument("--serve-streams", type=int, default=256)
@@ -757,7 +854,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (streams would be sharded "
-              "across GPUs with no exchange, see DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "copy":
         res = run_copy(args)
@@ -765,6 +862,8 @@ def main():
         res = run_serve(args)
     elif args.workload == "detect":
         res = run_detect(args)
+    elif args.workload == "sweep":
+        res = run_sweep(args)
     elif args.workload == "pair":
         res = run_pair(args)
     elif args.workload in ("stereo", "stereo16"):

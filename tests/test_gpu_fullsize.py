@@ -1,0 +1,121 @@
+"""Parity with the FP64 oracle at full workload sizes, through the prepared
+batch in the execution shape the autotuner picks (the launch the benchmark
+times).
+
+* the 64-stream batched workload (resolutions 640x480 .. 1920x1080, U[150,
+  1500] keypoints, seed 0): every keypoint of every stream, float32 and
+  binary16 storage;
+* the corners of the keypoint-count / resolution sweep (160 and 1500
+  keypoints per frame at 640x480 and 1920x1080).
+
+The oracle tracks each stream on all host threads; the comparison rule is
+``parity.compare`` (status and iteration counts equal away from decision
+thresholds, end points within 1e-3 px).  Binary16 storage is compared with
+the oracle's binary16 mode (same rule) and with the unrounded oracle (p99
+within 1e-2 px).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2607_01757_amd import lk as _lk
+    return _lk
+
+
+@pytest.fixture(scope="module")
+def ctx(lk):
+    c = lk.lk_context_create(0, 0)
+    yield c
+    lk.lk_context_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def streams64():
+    return synth.batch_streams(0, n_streams=64)
+
+
+def run_prepared(lk, ctx, streams, storage, win=21, levels=3, fb=0.0):
+    """One tuned, graph-captured step: new-frame pyramids + every pair."""
+    import torch
+    prev = [torch.from_numpy(s.prev).cuda() for s in streams]
+    nxt = [torch.from_numpy(s.next).cuda() for s in streams]
+    pp = [lk.lk_pyramid_create(ctx, s.width, s.height, levels, storage) for s in streams]
+    pn = [lk.lk_pyramid_create(ctx, s.width, s.height, levels, storage) for s in streams]
+    lk.lk_build_pyramids(ctx, pp, prev)
+    counts = [len(s.pts) for s in streams]
+    offs = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(int)
+    n = int(sum(counts))
+    pts = torch.from_numpy(np.concatenate([s.pts for s in streams])).cuda()
+    pairs = [(a, b, int(o), c) for a, b, o, c in zip(pp, pn, offs, counts)]
+    prm = lk.make_params(win, levels, 30, 0.01, 1e-6, fb)
+    out = lk.outputs(n, levels, with_iters=True)
+    b = lk.lk_batch_create(ctx, pn, nxt, pairs, pts, None, prm, *out, config=lk.lk_exec_config(0, 4, 1, 0))
+    cfg, _ = lk.lk_batch_tune(b, reps=2)
+    for t in out:
+        t.zero_()
+    lk.lk_batch_run(b)
+    torch.cuda.synchronize()
+    res = [t.cpu().numpy() for t in out]
+    lk.lk_batch_destroy(b)
+    for p in pp + pn:
+        lk.lk_pyramid_destroy(p)
+    print("tuned: persistent=%d blocks_per_cu=%d, %d keypoints" % (cfg.persistent, cfg.blocks_per_cu, n),
+          flush=True)
+    return res, offs, counts
+
+
+def check_streams(streams, res, offs, counts, *, win=21, levels=3, f16=False):
+    n_ok = 0
+    worst = 0.0
+    errs64 = []
+    for s, o, c in zip(streams, offs, counts):
+        g = tuple(x[o:o + c] for x in res)
+        r = oracle.track(s.prev, s.next, s.pts, win=win, levels=levels, min_eig=1e-6, f16=f16, nthreads=THREADS)
+        rep = compare(*g, r)
+        n_ok += rep.compared_ok
+        worst = max(worst, rep.max_err)
+        if f16:
+            r64 = oracle.track(s.prev, s.next, s.pts, win=win, levels=levels, min_eig=1e-6, nthreads=THREADS)
+            both = (g[1] == 0) & (r64.status == 0)
+            errs64.append(np.abs(g[0][both] - r64.pts[both]).max(axis=1))
+    return n_ok, worst, (np.concatenate(errs64) if errs64 else None)
+
+
+def test_batched_workload_all_keypoints_f32(lk, ctx, streams64):
+    res, offs, counts = run_prepared(lk, ctx, streams64, 0)
+    n_ok, worst, _ = check_streams(streams64, res, offs, counts)
+    print("64 streams, %d keypoints: %d compared, max end-point error %.3g px" % (sum(counts), n_ok, worst))
+    assert n_ok >= 0.9 * sum(counts)
+
+
+def test_batched_workload_all_keypoints_f16(lk, ctx, streams64):
+    res, offs, counts = run_prepared(lk, ctx, streams64, 1)
+    n_ok, worst, e64 = check_streams(streams64, res, offs, counts, f16=True)
+    print("binary16: %d compared with the binary16 oracle (max %.3g px); vs FP64: max %.4g p99 %.4g px"
+          % (n_ok, worst, e64.max(), np.percentile(e64, 99)))
+    assert n_ok >= 0.9 * sum(counts)
+    assert np.percentile(e64, 99) <= 1e-2
+
+
+@pytest.mark.parametrize("res_wh,kp", [((1920, 1080), 1500), ((640, 480), 160), ((1920, 1080), 160),
+                                       ((640, 480), 1500)])
+def test_sweep_corners(lk, ctx, res_wh, kp):
+    streams = synth.batch_streams(11, n_streams=6, kp_range=(kp, kp), resolutions=(res_wh,))
+    res, offs, counts = run_prepared(lk, ctx, streams, 0)
+    n_ok, worst, _ = check_streams(streams, res, offs, counts)
+    print("%dx%d, %d keypoints per frame: %d compared, max %.3g px" % (res_wh + (kp, n_ok, worst)))
+    assert n_ok >= 0.9 * sum(counts)
