@@ -73,6 +73,20 @@ GFTT_MUTANTS = [
 
 PINS = ["tests/test_oracle_primitives.py", "tests/test_oracle_tracker.py", "tests/test_oracle_gftt.py"]
 
+# planted in a copy of oracle/pool.py (the track-pool lifecycle)
+POOL_SRC = os.path.join(ROOT, "oracle", "pool.py")
+POOL_MUTANTS = [
+    ("pool carry keeps the lost points", "keep = np.asarray(status) == OK", "keep = np.asarray(status) != OK"),
+    ("pool top-up ignores the survivors' count", "room = max(int(target) - s, 0)", "room = max(int(target), 0)"),
+    ("pool top-up ignores the survivors' positions", "occupied=surv_pts if s else None)", "occupied=None)"),
+    ("pool identities for gated-out candidates", "        if not keep[i]:\n            continue\n", ""),
+    ("pool identities restart at zero", "nid = int(next_id)", "nid = 0"),
+    ("pool gate ignored", "keep = np.ones(n, bool) if gate_status is None else (np.asarray(gate_status) == OK)",
+     "keep = np.ones(n, bool)"),
+    ("pool stats carried/new swapped", "stats = (n0, len(si), len(ci) - len(si), len(ids))",
+     "stats = (n0, len(ci) - len(si), len(si), len(ids))"),
+]
+
 
 @pytest.fixture(scope="module")
 def workdir():
@@ -103,3 +117,24 @@ def test_pins_catch_mutant(workdir, name, old, new):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "pins did not catch: " + name
+
+
+@pytest.mark.parametrize("name,old,new", POOL_MUTANTS, ids=[m[0] for m in POOL_MUTANTS])
+def test_pool_pins_catch_mutant(workdir, name, old, new):
+    text = open(POOL_SRC).read()
+    assert text.count(old) == 1, "mutation site not found: " + name
+    src = os.path.join(workdir, "pool_mut_%d.py" % (abs(hash(name)) % 10 ** 8))
+    open(src, "w").write(text.replace(old, new))
+    env = dict(os.environ, LKO_POOL_SRC=src)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_pool.py"], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "pins did not catch: " + name
+
+
+def test_unplanted_pool_copy_passes(workdir):
+    src = os.path.join(workdir, "pool_copy.py")
+    open(src, "w").write(open(POOL_SRC).read())
+    env = dict(os.environ, LKO_POOL_SRC=src)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_pool.py"], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:]
