@@ -275,6 +275,83 @@ lk_result lk_detect_corners(lk_detector *det, const lk_gftt_frame *h_frames, int
                             const lk_gftt_params *params, lk_stream stream);
 lk_result lk_detector_destroy(lk_detector *det);   /* waits for the device */
 
+/* ---- track pools (the track lifecycle after LK) ---------------------------
+ * A pool keeps, for each of n_streams camera streams, up to `cap` live tracks
+ * on the device: position, 64-bit identity and, in stereo mode, the position
+ * in the right camera.  One lifecycle step per frame, for any subset of the
+ * streams.  Associated features keep their identity and unmatched new
+ * detections start new tracks (Sec. III-C, feature matching); in stereo mode
+ * only features that pass the cross-camera optical-flow check enter the
+ * temporal pool, in mono mode the pool is carried over by temporal tracking
+ * alone (Sec. V, the Botanic Garden discussion).  One step of stream s:
+ *   1. temporal pass: its live tracks are tracked from `prev` to `next`
+ *      (lk_track with the temporal parameters); with prev NULL (a first
+ *      frame) there is no pass and every live track ends;
+ *   2. carry-over: tracks with status LK_OK move to their end points and keep
+ *      their identities, in pool order; the others end;
+ *   3. top-up: corners of `next`'s level 0 (lk_detect_corners with the
+ *      detection parameters and the survivors as occupied points) are
+ *      appended in rank order until there are detect->max_corners candidates
+ *      (none when the survivors already reach it);
+ *   4. gate, when `right` is given: every candidate is tracked from `next` to
+ *      `right` with the stereo parameters (forward-backward check as set) and
+ *      only those with status LK_OK stay, with their right-camera positions;
+ *   5. commit: admitted new candidates take the stream's next identities in
+ *      order; identities start at 0 and are never reused.
+ * The result is the composition of lk_track and lk_detect_corners on the same
+ * inputs.  Nothing returns to the host: counts, identities and statistics are
+ * read from the state arrays when the caller wants them.
+ *
+ * State (caller-owned device arrays, see lk_pool_state): the live tracks of
+ * stream s are entries [s cap, s cap + count[s]).  count and next_id must be
+ * zero before the first step (or use lk_pool_reset).  Scratch: the
+ * intermediate results of a step live in pool-owned device memory, or in
+ * caller arrays when lk_pool_create gets an lk_pool_scratch (then they can be
+ * read after the step).  Steps on one pool must be ordered on one stream. */
+typedef struct lk_pool lk_pool;
+
+typedef struct {
+    float *pts;              /* n_streams x cap x 2 (x, y) */
+    int64_t *ids;            /* n_streams x cap */
+    float *right;            /* n_streams x cap x 2: right-camera positions; nullable if no step is gated */
+    int32_t *count;          /* n_streams: live tracks */
+    int64_t *next_id;        /* n_streams: next unused identity */
+    int32_t *stats;          /* n_streams x 4, nullable: of the stream's last step, the previous count,
+                                the carried tracks, the new candidates, the admitted tracks */
+} lk_pool_state;
+
+typedef struct {             /* every array n_streams x cap (x 2 for positions), device */
+    float *t_pts;            /* temporal pass over the previous pool: end points */
+    uint8_t *t_status;       /*   and status */
+    float *c_pts;            /* candidates: survivors, then new corners */
+    int64_t *c_ids;          /*   identities (-1: new) */
+    int32_t *c_count;        /* n_streams: candidates */
+    float *s_pts;            /* gate pass over the candidates: right-camera end points */
+    uint8_t *s_status;       /*   and status */
+} lk_pool_scratch;
+
+typedef struct {
+    int32_t stream;               /* pool stream index, 0..n_streams-1, distinct within a call */
+    int32_t reserved;             /* must be 0 */
+    const lk_pyramid *prev;       /* left pyramid of frame t-1, or NULL */
+    const lk_pyramid *next;       /* left pyramid of frame t; its level 0 is the detection frame */
+    const lk_pyramid *right;      /* right pyramid of frame t, or NULL (no gate) */
+} lk_pool_frame;
+
+/* n_streams >= 1, cap in [1, LK_GFTT_MAX_CORNERS], n_streams x cap <= 2^26;
+ * max_pixels: level-0 pixels of all frames of one step, at most (the
+ * detector's workspace).  scratch: nullable. */
+lk_result lk_pool_create(lk_context *ctx, int32_t n_streams, int32_t cap, int64_t max_pixels,
+                         const lk_pool_state *state, const lk_pool_scratch *scratch, lk_pool **out);
+/* temporal: needed when some frame has prev, stereo: when some frame has
+ * right (use_guess must be 0 in both); detect->max_corners <= cap is the
+ * top-up target.  Only enqueues work. */
+lk_result lk_pool_step(lk_pool *pool, const lk_pool_frame *h_frames, int32_t n_frames, const lk_params *temporal,
+                       const lk_params *stereo, const lk_gftt_params *detect, lk_stream stream);
+/* Every stream empty, identities from 0 (enqueued). */
+lk_result lk_pool_reset(lk_pool *pool, lk_stream stream);
+lk_result lk_pool_destroy(lk_pool *pool);   /* waits for the device */
+
 /* ---- serving (continuous batching over many camera streams) --------------
  * A server owns, per camera stream, device frame buffers and two resident
  * pyramids (the previous frame's and the current one's) plus pinned host

@@ -22,6 +22,74 @@ struct lk_detector {
     GfttPeak *d_cand = nullptr;
 };
 
+namespace lkmi {
+
+lk_result check_gftt_params(const lk_gftt_params *p)
+{
+    if (p->radius < 0 || p->radius > 3) return fail(LK_ERR_INVALID_ARG, "radius must be in [0, 3]");
+    if (p->min_dist < 0 || p->min_dist > 32767) return fail(LK_ERR_INVALID_ARG, "min_dist must be in [0, 32767]");
+    if (p->max_corners < 0 || p->max_corners > LK_GFTT_MAX_CORNERS)
+        return fail(LK_ERR_INVALID_ARG, "max_corners must be in [0, %d]", LK_GFTT_MAX_CORNERS);
+    if (p->border < 0) return fail(LK_ERR_INVALID_ARG, "border must be >= 0");
+    if (!(p->quality >= 0.0) || !std::isfinite(p->quality))
+        return fail(LK_ERR_INVALID_ARG, "quality must be finite and >= 0");
+    return LK_SUCCESS;
+}
+
+lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const lk_gftt_params *p, hipStream_t s)
+{
+    lk_result r = check_gftt_params(p);
+    if (r != LK_SUCCESS) return r;
+    const int n_frames = (int)jobs.size();
+    if (n_frames > det->max_frames)
+        return fail(LK_ERR_INVALID_ARG, "%d frames exceed the detector's %d", n_frames, det->max_frames);
+    if (n_frames == 0) return LK_SUCCESS;
+    int64_t pixels = 0;
+    long long tiles = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        GfttJob &J = jobs[f];
+        if (J.w < 3 || J.h < 3 || J.w > 32768 || J.h > 32768)
+            return fail(LK_ERR_INVALID_ARG, "frame %d: size %dx%d not in [3, 32768]^2", f, J.w, J.h);
+        if (J.pitch < J.w) return fail(LK_ERR_INVALID_ARG, "frame %d: pitch < width", f);
+        J.tiles_x = (J.w + kGfttTileW - 1) / kGfttTileW;
+        J.tile_begin = (int32_t)tiles;
+        J.peaks = det->d_peaks + pixels;
+        J.n_peaks = det->d_counts + 2 * f;
+        J.cand = det->d_cand + pixels;
+        J.n_cand = det->d_counts + 2 * f + 1;
+        J.max_bits = det->d_max + f;
+        pixels += (int64_t)J.w * J.h;
+        tiles += (long long)J.tiles_x * ((J.h + kGfttTileH - 1) / kGfttTileH);
+    }
+    if (pixels > det->max_pixels)
+        return fail(LK_ERR_INVALID_ARG, "%lld pixels exceed the detector's %lld", (long long)pixels,
+                    (long long)det->max_pixels);
+    if (tiles > 0x7FFFFFFFLL) return fail(LK_ERR_INVALID_ARG, "too many tiles");
+    (void)hipSetDevice(det->ctx->device);
+    // jobs, then the job of every tile
+    std::vector<int32_t> tile_job((size_t)tiles);
+    for (int f = 0; f < n_frames; ++f) {
+        const long long n = (long long)jobs[f].tiles_x * ((jobs[f].h + kGfttTileH - 1) / kGfttTileH);
+        std::fill(tile_job.begin() + jobs[f].tile_begin, tile_job.begin() + jobs[f].tile_begin + n, f);
+    }
+    StagingRing::Slot *slot = nullptr;
+    const size_t jbytes = (jobs.size() * sizeof(GfttJob) + 15) & ~size_t(15);
+    const size_t bytes = jbytes + tile_job.size() * sizeof(int32_t);
+    r = det->ctx->staging.acquire(bytes, &slot);
+    if (r != LK_SUCCESS) return r;
+    std::memcpy(slot->host, jobs.data(), jobs.size() * sizeof(GfttJob));
+    std::memcpy(static_cast<char *>(slot->host) + jbytes, tile_job.data(), tile_job.size() * sizeof(int32_t));
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(detector jobs)");
+    e = launch_gftt(static_cast<const GfttJob *>(slot->dev),
+                    reinterpret_cast<const int32_t *>(static_cast<const char *>(slot->dev) + jbytes), n_frames,
+                    (int)tiles, p->radius, p->border, p->quality, p->min_dist, p->max_corners, s);
+    (void)hipEventRecord(slot->done, s);
+    return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "detector launch");
+}
+
+}  // namespace lkmi
+
 extern "C" {
 
 lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pixels, lk_detector **out)
@@ -64,22 +132,10 @@ lk_result lk_detect_corners(lk_detector *det, const lk_gftt_frame *h_frames, int
         return fail(LK_ERR_INVALID_ARG, "n_frames %d not in [0, %d]", n_frames, det->max_frames);
     if (n_frames == 0) return LK_SUCCESS;
     if (!h_frames) return fail(LK_ERR_INVALID_ARG, "h_frames is NULL");
-    if (p->radius < 0 || p->radius > 3) return fail(LK_ERR_INVALID_ARG, "radius must be in [0, 3]");
-    if (p->min_dist < 0 || p->min_dist > 32767) return fail(LK_ERR_INVALID_ARG, "min_dist must be in [0, 32767]");
-    if (p->max_corners < 0 || p->max_corners > LK_GFTT_MAX_CORNERS)
-        return fail(LK_ERR_INVALID_ARG, "max_corners must be in [0, %d]", LK_GFTT_MAX_CORNERS);
-    if (p->border < 0) return fail(LK_ERR_INVALID_ARG, "border must be >= 0");
-    if (!(p->quality >= 0.0) || !std::isfinite(p->quality))
-        return fail(LK_ERR_INVALID_ARG, "quality must be finite and >= 0");
     std::vector<GfttJob> jobs(n_frames);
-    int64_t pixels = 0;
-    long long tiles = 0;
     for (int f = 0; f < n_frames; ++f) {
         const lk_gftt_frame &F = h_frames[f];
         if (!F.img || !F.out_xy || !F.count) return fail(LK_ERR_INVALID_ARG, "frame %d: NULL img, out_xy or count", f);
-        if (F.w < 3 || F.h < 3 || F.w > 32768 || F.h > 32768)
-            return fail(LK_ERR_INVALID_ARG, "frame %d: size %dx%d not in [3, 32768]^2", f, F.w, F.h);
-        if (F.pitch < F.w) return fail(LK_ERR_INVALID_ARG, "frame %d: pitch < width", f);
         if (F.n_occupied < 0 || (F.n_occupied > 0 && !F.occupied))
             return fail(LK_ERR_INVALID_ARG, "frame %d: bad occupied points", f);
         GfttJob &J = jobs[f];
@@ -87,47 +143,13 @@ lk_result lk_detect_corners(lk_detector *det, const lk_gftt_frame *h_frames, int
         J.w = F.w;
         J.h = F.h;
         J.pitch = F.pitch;
-        J.tiles_x = (F.w + kGfttTileW - 1) / kGfttTileW;
-        J.tile_begin = (int32_t)tiles;
         J.n_occupied = F.n_occupied;
         J.occupied = F.occupied;
-        J.peaks = det->d_peaks + pixels;
-        J.n_peaks = det->d_counts + 2 * f;
-        J.cand = det->d_cand + pixels;
-        J.n_cand = det->d_counts + 2 * f + 1;
-        J.max_bits = det->d_max + f;
         J.out_xy = F.out_xy;
         J.count = F.count;
         J.response = F.response;
-        pixels += (int64_t)F.w * F.h;
-        tiles += (long long)J.tiles_x * ((F.h + kGfttTileH - 1) / kGfttTileH);
     }
-    if (pixels > det->max_pixels)
-        return fail(LK_ERR_INVALID_ARG, "%lld pixels exceed the detector's %lld", (long long)pixels,
-                    (long long)det->max_pixels);
-    if (tiles > 0x7FFFFFFFLL) return fail(LK_ERR_INVALID_ARG, "too many tiles");
-    (void)hipSetDevice(det->ctx->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // jobs, then the job of every tile
-    std::vector<int32_t> tile_job((size_t)tiles);
-    for (int f = 0; f < n_frames; ++f) {
-        const long long n = (long long)jobs[f].tiles_x * ((jobs[f].h + kGfttTileH - 1) / kGfttTileH);
-        std::fill(tile_job.begin() + jobs[f].tile_begin, tile_job.begin() + jobs[f].tile_begin + n, f);
-    }
-    StagingRing::Slot *slot = nullptr;
-    const size_t jbytes = (jobs.size() * sizeof(GfttJob) + 15) & ~size_t(15);
-    const size_t bytes = jbytes + tile_job.size() * sizeof(int32_t);
-    lk_result r = det->ctx->staging.acquire(bytes, &slot);
-    if (r != LK_SUCCESS) return r;
-    std::memcpy(slot->host, jobs.data(), jobs.size() * sizeof(GfttJob));
-    std::memcpy(static_cast<char *>(slot->host) + jbytes, tile_job.data(), tile_job.size() * sizeof(int32_t));
-    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(detector jobs)");
-    e = launch_gftt(static_cast<const GfttJob *>(slot->dev),
-                    reinterpret_cast<const int32_t *>(static_cast<const char *>(slot->dev) + jbytes), n_frames,
-                    (int)tiles, p->radius, p->border, p->quality, p->min_dist, p->max_corners, s);
-    (void)hipEventRecord(slot->done, s);
-    return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "detector launch");
+    return lkmi::detector_enqueue(det, jobs, p, static_cast<hipStream_t>(stream));
 }
 
 lk_result lk_detector_destroy(lk_detector *det)

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     const double md2d = (double)md2;
     const bool spaced = min_dist >= 2;         // distinct pixels are always >= 1 apart
     const GfttPeak *cand = J.cand;
-    const int n_occ = J.n_occupied;
+    const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
 
     for (int k = tid; k < n_occ && k < OCC_LDS; k += SBLOCK) sm.occ[k] = make_float2(J.occupied[2 * k], J.occupied[2 * k + 1]);
     int remaining = np;

@@ -46,6 +46,7 @@ struct BatchItem {
     int64_t pt_offset;
     int32_t n;
     int32_t first_wave;        // prefix sum of n over earlier items
+    const int32_t *limit;      // nullable: only the first *limit of the n points are live (a count on the device)
 };
 
 // A descriptor to be copied to device memory by k_write_descs.
@@ -102,6 +103,7 @@ struct GfttJob {
     int32_t tiles_x, tile_begin;
     int32_t n_occupied;
     const float *occupied;
+    const int32_t *n_occupied_dev;   // nullable: the number of occupied points, read on the device
     GfttPeak *peaks;                 // local maxima with R > 0, capacity w * h
     int32_t *n_peaks;
     GfttPeak *cand;                  // those above the quality threshold, capacity w * h
@@ -110,6 +112,30 @@ struct GfttJob {
     float *out_xy;
     int32_t *count;
     double *response;                // nullable
+};
+
+// One stream's track pool in one lifecycle step (all pointers are that
+// stream's slices of the pool's device memory).
+struct PoolJob {
+    float *pts;                  // cap x 2: live tracks (read by the temporal pass, rewritten by the commit)
+    int64_t *ids;                // cap
+    float *right;                // cap x 2: stereo positions of the live tracks
+    int32_t *count;              // live tracks
+    int64_t *next_id;            // next unused identity
+    const float *t_pts;          // temporal pass: end points and status of the live tracks
+    const uint8_t *t_status;
+    float *c_pts;                // candidates: survivors, then new corners
+    int64_t *c_ids;
+    int32_t *c_count;
+    const float *d_xy;           // detector output on the new frame and its count
+    const int32_t *d_count;
+    const float *s_pts;          // cross-camera pass over the candidates
+    const uint8_t *s_status;
+    int32_t *stats;              // previous count, carried, new candidates, admitted
+    int32_t tracked;             // the temporal pass ran for this stream
+    int32_t gated;               // the cross-camera pass ran for this stream
+    int32_t target;              // top up to this many tracks (<= cap)
+    int32_t cap;                 // entries of every per-stream array
 };
 
 constexpr int kGfttTileW = 64, kGfttTileH = 16;
@@ -160,6 +186,11 @@ hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int to
 // Detection of every frame in d_jobs (reset, peaks, selection: three launches).
 hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int radius,
                        int border, double quality, int min_dist, int max_corners, hipStream_t stream);
+// Track-pool lifecycle kernels (lk_pool_kernels.hip), one workgroup per stream.
+hipError_t launch_pool_carry(const PoolJob *d_jobs, int n, hipStream_t stream);
+hipError_t launch_pool_append(const PoolJob *d_jobs, int n, hipStream_t stream);
+hipError_t launch_pool_commit(const PoolJob *d_jobs, int n, hipStream_t stream);
+hipError_t launch_pool_reset(int32_t *d_count, int64_t *d_next_id, int n, hipStream_t stream);
 hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream);
 
 }  // namespace lkmi

@@ -1200,6 +1200,7 @@ void k_track_batched(const BatchItem *items, int n_items, TrackArgs a)
     }
     lo = uniform_i(lo);
     const BatchItem &it = items[lo];
+    if (it.limit && wave - it.first_wave >= *it.limit) return;      // past the item's live count
     const int idx = (int)(it.pt_offset + (wave - it.first_wave));
     track_point<ST, G>(*it.prev, *it.next, a, idx, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
 }
@@ -1233,6 +1234,7 @@ void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *coun
             }
             lo = uniform_i(lo);
             const BatchItem &it = items[lo];
+            if (it.limit && wave - it.first_wave >= *it.limit) continue;
             const int idx = (int)(it.pt_offset + (wave - it.first_wave));
             track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
         }

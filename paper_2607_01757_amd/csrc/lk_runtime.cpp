@@ -454,7 +454,7 @@ lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const l
             return fail(LK_ERR_INVALID_ARG, "pair %d: all pairs of one batch must share a storage", i);
         *storage = p.prev->desc.storage;
         min_levels = std::min(min_levels, std::min(p.prev->desc.levels, p.next->desc.levels));
-        BatchItem it;
+        BatchItem it{};
         it.prev = p.prev->d_desc;
         it.next = p.next->d_desc;
         it.pt_offset = p.pt_offset;

@@ -79,4 +79,8 @@ lk_result enqueue_build(lk_context *ctx, lk_pyramid *const *pyrs, int n, hipStre
 // more levels, one down job per remaining level, gradient planes (binary16).
 void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<DownJob> *down_by_level,
                   std::vector<GradJob> *grads);
+lk_result check_gftt_params(const lk_gftt_params *p);
+// Detection of every job (img, w, h, pitch, occupied points, out_xy, count,
+// response filled in by the caller; tiles and workspace slices here).
+lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const lk_gftt_params *p, hipStream_t s);
 }  // namespace lkmi

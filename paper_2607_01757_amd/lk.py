@@ -29,6 +29,7 @@ ABI_SYMBOLS = (
     "lk_server_create", "lk_server_open_stream", "lk_server_submit", "lk_server_poll", "lk_server_close_stream",
     "lk_server_get_stats", "lk_server_destroy",
     "lk_detector_create", "lk_detect_corners", "lk_detector_destroy",
+    "lk_pool_create", "lk_pool_step", "lk_pool_reset", "lk_pool_destroy",
 )
 LK_GFTT_MAX_CORNERS = 4096
 
@@ -84,6 +85,21 @@ class lk_gftt_frame(C.Structure):
                 ("count", C.c_void_p), ("response", C.c_void_p)]
 
 
+class lk_pool_state(C.Structure):
+    _fields_ = [("pts", C.c_void_p), ("ids", C.c_void_p), ("right", C.c_void_p), ("count", C.c_void_p),
+                ("next_id", C.c_void_p), ("stats", C.c_void_p)]
+
+
+class lk_pool_scratch(C.Structure):
+    _fields_ = [("t_pts", C.c_void_p), ("t_status", C.c_void_p), ("c_pts", C.c_void_p), ("c_ids", C.c_void_p),
+                ("c_count", C.c_void_p), ("s_pts", C.c_void_p), ("s_status", C.c_void_p)]
+
+
+class lk_pool_frame(C.Structure):
+    _fields_ = [("stream", C.c_int32), ("reserved", C.c_int32), ("prev", C.c_void_p), ("next", C.c_void_p),
+                ("right", C.c_void_p)]
+
+
 class LKError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("lk error %d: %s" % (code, msg))
@@ -126,6 +142,12 @@ def _load():
         "lk_detector_create": (res, [vp, i32, C.c_int64, C.POINTER(vp)]),
         "lk_detect_corners": (res, [vp, C.POINTER(lk_gftt_frame), i32, C.POINTER(lk_gftt_params), vp]),
         "lk_detector_destroy": (res, [vp]),
+        "lk_pool_create": (res, [vp, i32, i32, C.c_int64, C.POINTER(lk_pool_state), C.POINTER(lk_pool_scratch),
+                                 C.POINTER(vp)]),
+        "lk_pool_step": (res, [vp, C.POINTER(lk_pool_frame), i32, C.POINTER(lk_params), C.POINTER(lk_params),
+                               C.POINTER(lk_gftt_params), vp]),
+        "lk_pool_reset": (res, [vp, vp]),
+        "lk_pool_destroy": (res, [vp]),
     }
     for name, (rt, at) in sig.items():
         f = getattr(lib, name)
@@ -358,7 +380,62 @@ def lk_detector_destroy(det):
     _check(lib.lk_detector_destroy(det))
 
 
+def lk_pool_create(ctx, n_streams: int, cap: int, max_pixels: int, state: dict, scratch: dict | None = None):
+    """state / scratch: dicts of CUDA tensors named like the fields of
+    lk_pool_state / lk_pool_scratch (see pool_state, pool_scratch)."""
+    st = lk_pool_state(*[_ptr(state.get(k)) for k, _ in lk_pool_state._fields_])
+    sc = None if scratch is None else lk_pool_scratch(*[_ptr(scratch[k]) for k, _ in lk_pool_scratch._fields_])
+    out = C.c_void_p()
+    _check(lib.lk_pool_create(ctx, n_streams, cap, max_pixels, C.byref(st), C.byref(sc) if sc is not None else None,
+                              C.byref(out)))
+    return out
+
+
+def lk_pool_step(pool, frames, temporal: lk_params | None, stereo: lk_params | None, detect: lk_gftt_params,
+                 stream=None):
+    """frames: sequence of (stream index, prev pyramid or None, next pyramid,
+    right pyramid or None)."""
+    n = len(frames)
+    F = (lk_pool_frame * max(n, 1))()
+    for i, (sid, prev, nxt, right) in enumerate(frames):
+        F[i] = lk_pool_frame(sid, 0, _hv(prev) if prev is not None else None, _hv(nxt),
+                             _hv(right) if right is not None else None)
+    _check(lib.lk_pool_step(pool, F, n, C.byref(temporal) if temporal is not None else None,
+                            C.byref(stereo) if stereo is not None else None, C.byref(detect), _stream(stream)))
+
+
+def lk_pool_reset(pool, stream=None):
+    _check(lib.lk_pool_reset(pool, _stream(stream)))
+
+
+def lk_pool_destroy(pool):
+    _check(lib.lk_pool_destroy(pool))
+
+
 # ---------------------------------------------------------------- helpers
+
+def pool_state(n_streams: int, cap: int, device="cuda") -> dict:
+    """Zeroed state tensors of a pool (every stream empty)."""
+    import torch
+    return {"pts": torch.zeros((n_streams, cap, 2), dtype=torch.float32, device=device),
+            "ids": torch.zeros((n_streams, cap), dtype=torch.int64, device=device),
+            "right": torch.zeros((n_streams, cap, 2), dtype=torch.float32, device=device),
+            "count": torch.zeros((n_streams,), dtype=torch.int32, device=device),
+            "next_id": torch.zeros((n_streams,), dtype=torch.int64, device=device),
+            "stats": torch.zeros((n_streams, 4), dtype=torch.int32, device=device)}
+
+
+def pool_scratch(n_streams: int, cap: int, device="cuda") -> dict:
+    """Caller-owned scratch of a pool, readable after each step."""
+    import torch
+    return {"t_pts": torch.zeros((n_streams, cap, 2), dtype=torch.float32, device=device),
+            "t_status": torch.zeros((n_streams, cap), dtype=torch.uint8, device=device),
+            "c_pts": torch.zeros((n_streams, cap, 2), dtype=torch.float32, device=device),
+            "c_ids": torch.zeros((n_streams, cap), dtype=torch.int64, device=device),
+            "c_count": torch.zeros((n_streams,), dtype=torch.int32, device=device),
+            "s_pts": torch.zeros((n_streams, cap, 2), dtype=torch.float32, device=device),
+            "s_status": torch.zeros((n_streams, cap), dtype=torch.uint8, device=device)}
+
 
 def gftt_params(radius=1, min_dist=30, max_corners=200, border=0, quality=0.01) -> lk_gftt_params:
     return lk_gftt_params(radius, min_dist, max_corners, border, quality)

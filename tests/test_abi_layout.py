@@ -22,6 +22,9 @@ STRUCTS = {
     "lk_server_stats": ["frames", "batches", "points", "resident_bytes", "open_streams", "reserved"],
     "lk_gftt_params": ["radius", "min_dist", "max_corners", "border", "quality"],
     "lk_gftt_frame": ["img", "w", "h", "pitch", "n_occupied", "occupied", "out_xy", "count", "response"],
+    "lk_pool_state": ["pts", "ids", "right", "count", "next_id", "stats"],
+    "lk_pool_scratch": ["t_pts", "t_status", "c_pts", "c_ids", "c_count", "s_pts", "s_status"],
+    "lk_pool_frame": ["stream", "reserved", "prev", "next", "right"],
 }
 
 
