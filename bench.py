@@ -731,6 +731,115 @@ def run_detect(args):
     return result
 
 
+def run_frontend(args):
+    """The front-end step of every camera rig after the tracker: track pools
+    over 64 stereo (or mono) streams.  One step = pyramids of the left and
+    right frames of every stream (one batched build) + one lifecycle step of
+    every pool (temporal pass, carry-over, Shi-Tomasi top-up to the cap,
+    cross-camera gate, new identities)."""
+    import torch
+    import synth
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2607_01757_amd import lk
+
+    n_str, distinct, reps_per = args.streams, 16, 4
+    cap = args.pool_cap
+    stereo = not args.mono
+    t0 = time.time()
+    res = [synth.RESOLUTIONS[q % len(synth.RESOLUTIONS)] for q in range(distinct)]
+    seqs = [synth.StereoSequence(100 + q, width=w, height=h, n_frames=1000) for q, (w, h) in enumerate(res)]
+    span = 8                                   # frames each stream plays back and forth
+    n_frames = span + reps_per - 1
+    jobs = [(q, f, c) for q in range(distinct) for f in range(n_frames) for c in ((0, 1) if stereo else (0,))]
+    with ThreadPoolExecutor(8) as ex:
+        rendered = list(ex.map(lambda j: seqs[j[0]].frame(j[1], j[2]), jobs))
+    dev = {j: torch.from_numpy(im).cuda() for j, im in zip(jobs, rendered)}
+    log("frontend: %d sequences x %d frames rendered in %.1fs" % (distinct, n_frames, time.time() - t0))
+
+    def frame_of(stream, step):            # back and forth over `span` frames, offset per replica
+        p = step % (2 * span - 2)
+        p = p if p < span else 2 * span - 2 - p
+        return stream % distinct, p + stream // distinct
+
+    ctx = lk.lk_context_create(0, 0)
+    dims = [res[i % distinct] for i in range(n_str)]
+    left = [[lk.lk_pyramid_create(ctx, w, h, 3, 0) for _ in range(2)] for (w, h) in dims]
+    right = [lk.lk_pyramid_create(ctx, w, h, 3, 0) for (w, h) in dims] if stereo else None
+    state = lk.pool_state(n_str, cap)
+    pool = lk.lk_pool_create(ctx, n_str, cap, sum(w * h for w, h in dims), state)
+    temporal = lk.make_params(21, 3, 30, 0.01, 1e-6, 0.0)
+    stereo_prm = lk.make_params(21, 3, 30, 0.01, 1e-6, 1.0)
+    det = lk.gftt_params(1, 20, cap, 8, 0.01)
+
+    def step(k):
+        pyrs, imgs, frames = [], [], []
+        for i in range(n_str):
+            q, f = frame_of(i, k)
+            cur = left[i][k & 1]
+            pyrs.append(cur)
+            imgs.append(dev[(q, f, 0)])
+            if stereo:
+                pyrs.append(right[i])
+                imgs.append(dev[(q, f, 1)])
+            frames.append((i, left[i][(k - 1) & 1] if k > 0 else None, cur, right[i] if stereo else None))
+        lk.lk_build_pyramids(ctx, pyrs, imgs)
+        lk.lk_pool_step(pool, frames, temporal, stereo_prm, det)
+
+    k = 0
+    for _ in range(max(args.warmup, 3)):
+        step(k)
+        k += 1
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    tw = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        step(k)
+        b.record()
+        k += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw
+    per = [a.elapsed_time(b) for a, b in evs]
+    # pool statistics and tracked points per step (untimed, synchronised)
+    prev_n = carried = cand = admitted = 0
+    counts = []
+    for _ in range(args.steps):
+        step(k)
+        k += 1
+        st = state["stats"].cpu().numpy().astype(np.int64)
+        prev_n += int(st[:, 0].sum()); carried += int(st[:, 1].sum())
+        cand += int((st[:, 1] + st[:, 2]).sum()); admitted += int(st[:, 3].sum())
+        counts.append(int(state["count"].sum().item()))
+    tracked_per_step = (prev_n + (cand if stereo else 0)) / args.steps
+    step_s = wall / args.steps
+    result = {
+        "metric": "front-end steps/sec with track pools (64 %s streams) + tracked keypoints/sec" % (
+            "stereo" if stereo else "mono"),
+        "value": n_str / step_s, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "frontend: %d %s streams (16 homography sequences {640x480..1920x1080}, 4 time "
+                               "offsets each, played back and forth), pools of %d tracks: pyramids of every "
+                               "frame + temporal LK, carry-over, Shi-Tomasi top-up (min distance 20), %sidentities;"
+                               " 21x21, 3 levels" % (n_str, "stereo" if stereo else "mono", cap,
+                                                     "cross-camera gate (FB 1 px), " if stereo else "")},
+        "p50_step_ms": percentile(per, 50), "p99_step_ms": percentile(per, 99),
+        "tracked_keypoints_per_s": tracked_per_step / step_s,
+        "forward_rate": carried / max(prev_n, 1),
+        "admitted_per_stream": admitted / args.steps / n_str,
+        "new_candidates_per_stream": (cand - carried) / args.steps / n_str,
+        "live_tracks_per_stream": float(np.mean(counts)) / n_str,
+    }
+    log("frontend: %.3f ms/step (p99 %.3f), %.3g tracked kp/s, forward rate %.4f, %.1f tracks per stream" %
+        (step_s * 1e3, result["p99_step_ms"], result["tracked_keypoints_per_s"], result["forward_rate"],
+         result["live_tracks_per_stream"]))
+    lk.lk_pool_destroy(pool)
+    for p in [p for pr in left for p in pr] + (right or []):
+        lk.lk_pyramid_destroy(p)
+    lk.lk_context_destroy(ctx)
+    return result
+
+
 SWEEP_KP = (160, 192, 256, 384, 512, 768, 1000, 1500)
 
 
@@ -836,7 +945,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "pair", "stereo", "stereo16", "serve",
-                                                           "detect", "sweep", "copy"])
+                                                           "detect", "sweep", "frontend", "copy"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--precision-frames", type=int, default=5)
     ap.add_argument("--serve-streams", type=int, default=256)
@@ -849,6 +958,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--gftt-corners", type=int, default=200)
+    ap.add_argument("--pool-cap", type=int, default=256, help="tracks per stream (frontend workload)")
+    ap.add_argument("--mono", action="store_true", help="frontend workload without the cross-camera gate")
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32",
                     help="pyramid storage of the batched workload")
     args = ap.parse_args()
@@ -864,6 +975,8 @@ def main():
         res = run_detect(args)
     elif args.workload == "sweep":
         res = run_sweep(args)
+    elif args.workload == "frontend":
+        res = run_frontend(args)
     elif args.workload == "pair":
         res = run_pair(args)
     elif args.workload in ("stereo", "stereo16"):

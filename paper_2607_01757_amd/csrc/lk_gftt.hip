@@ -277,6 +277,7 @@ constexpr int CAPW = kGfttWindow;             // window of peaks sorted in LDS
 constexpr int SBLOCK = 512;                   // threads of the selection workgroup
 constexpr int CHUNK = SBLOCK;                 // candidates decided together
 constexpr int OCC_LDS = 1024;                 // occupied points cached in LDS
+constexpr int OCC_GRID = 4096;                // cells of their grid
 
 struct Key {
     unsigned long long hi;   // bits of R (R > 0, so the bits order like R)
@@ -321,7 +322,9 @@ struct alignas(16) SelSmem {
     unsigned long long whi[CAPW];
     uint32_t wlo[CAPW];
     uint32_t taken[kGfttMaxCorners + 16];     // x | y << 16
-    float2 occ[OCC_LDS];
+    float2 occ[OCC_LDS];                       // the cached occupied points, grouped by grid cell
+    uint32_t occ_end[OCC_GRID];                // end of each cell's group in occ
+    uint32_t wsum[SBLOCK / 64];
     int32_t cx[CHUNK], cy[CHUNK];
     uint32_t hist[SBLOCK / 64][256];           // one histogram per wavefront
     unsigned long long cmask[CHUNK][CHUNK / 64];   // conflicts with better candidates of the chunk
@@ -366,7 +369,65 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     const GfttPeak *cand = J.cand;
     const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
 
-    for (int k = tid; k < n_occ && k < OCC_LDS; k += SBLOCK) sm.occ[k] = make_float2(J.occupied[2 * k], J.occupied[2 * k + 1]);
+    // The first OCC_LDS occupied points, grouped by the cells of a grid of
+    // cs x cs pixels with cs >= min_dist: a point closer than min_dist to an
+    // integer pixel lies in that pixel's cell or one of its 8 neighbours
+    // (points off the frame, or not finite, go to the nearest border cell),
+    // so a candidate checks only those 9 cells, with the same binary64 rule.
+    const int nl = n_occ < OCC_LDS ? n_occ : OCC_LDS;
+    int cs = min_dist > 1 ? min_dist : 1, gx, gy;
+    for (;;) {
+        gx = (W + cs - 1) / cs;
+        gy = (J.h + cs - 1) / cs;
+        if (gx * gy <= OCC_GRID) break;
+        cs += (cs >> 2) + 1;
+    }
+    const int ncell = gx * gy;
+    auto cell_of = [&](float ox, float oy) {
+        const float lim = (float)(2 * cs);
+        const int ix = (int)floorf(fminf(fmaxf(ox, -lim), (float)W + lim));
+        const int iy = (int)floorf(fminf(fmaxf(oy, -lim), (float)J.h + lim));
+        const int cx = ix < 0 ? 0 : min(ix / cs, gx - 1), cy = iy < 0 ? 0 : min(iy / cs, gy - 1);
+        return cy * gx + cx;
+    };
+    if (nl > 0) {
+        for (int k = tid; k < ncell; k += SBLOCK) sm.occ_end[k] = 0;
+        __syncthreads();
+        for (int k = tid; k < nl; k += SBLOCK) atomicAdd(&sm.occ_end[cell_of(J.occupied[2 * k], J.occupied[2 * k + 1])], 1u);
+        __syncthreads();
+        // exclusive prefix sum over the cells, 8 per thread
+        constexpr int PER = OCC_GRID / SBLOCK;
+        uint32_t v[PER], tsum = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = tid * PER + i;
+            v[i] = c < ncell ? sm.occ_end[c] : 0u;
+            tsum += v[i];
+        }
+        uint32_t incl = tsum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) sm.wsum[wv] = incl;
+        __syncthreads();
+        uint32_t run = incl - tsum;
+        for (int w = 0; w < wv; ++w) run += sm.wsum[w];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = tid * PER + i;
+            if (c < ncell) sm.occ_end[c] = run;
+            run += v[i];
+        }
+        __syncthreads();
+        // scatter: each cell's counter ends at the end of its group
+        for (int k = tid; k < nl; k += SBLOCK) {
+            const float ox = J.occupied[2 * k], oy = J.occupied[2 * k + 1];
+            const uint32_t at = atomicAdd(&sm.occ_end[cell_of(ox, oy)], 1u);
+            sm.occ[at] = make_float2(ox, oy);
+        }
+    }
     int remaining = np;
     int nt = 0;
     bool bounded = false;
@@ -514,24 +575,20 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             }
             // occupied points, 8 per step (binary64 distance)
             if (valid && n_occ > 0) {
-                const int nl = n_occ < OCC_LDS ? n_occ : OCC_LDS;
-                const float4 *o4 = reinterpret_cast<const float4 *>(sm.occ);
-                for (int q = 0; q < nl && !blocked; q += 8) {
-                    float ox[8], oy[8];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const float4 u = o4[q / 2 + v];
-                        ox[2 * v] = u.x; oy[2 * v] = u.y; ox[2 * v + 1] = u.z; oy[2 * v + 1] = u.w;
-                    }
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
+                const int ccx = x / cs, ccy = y / cs;
+                for (int yy = max(ccy - 1, 0); yy <= min(ccy + 1, gy - 1) && !blocked; ++yy) {
+                    const int c0 = yy * gx + max(ccx - 1, 0), c1 = yy * gx + min(ccx + 1, gx - 1);
+                    // the three cells of a row are consecutive groups
+                    const int b = c0 == 0 ? 0 : (int)sm.occ_end[c0 - 1], e = (int)sm.occ_end[c1];
+                    for (int q = b; q < e && !blocked; ++q) {
+                        const float2 o = sm.occ[q];
                         double dd;
                         {
 #pragma clang fp contract(off)
-                            const double dx = (double)x - (double)ox[i], dy = (double)y - (double)oy[i];
+                            const double dx = (double)x - (double)o.x, dy = (double)y - (double)o.y;
                             dd = dx * dx + dy * dy;
                         }
-                        blocked |= (q + i < nl) && (dd < md2d);
+                        blocked |= dd < md2d;
                     }
                 }
                 for (int q = OCC_LDS; q < n_occ && !blocked; ++q) {
