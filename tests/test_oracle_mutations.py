@@ -118,6 +118,41 @@ def test_pins_catch_mutant(workdir, name, old, new):
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "pins did not catch: " + name
 
+# planted in a copy of oracle/epipolar.py (the epipolar check)
+EPI_SRC = os.path.join(ROOT, "oracle", "epipolar.py")
+EPI_MUTANTS = [
+    ("epipolar system rows transposed", "np.stack([np.kron(xq[i], xp[i])", "np.stack([np.kron(xp[i], xq[i])"),
+    ("epipolar model left in normalized coordinates", "f = ki.T @ e @ ki", "f = e"),
+    ("epipolar line normalised with its offset", "np.sqrt(l[:, 0] ** 2 + l[:, 1] ** 2)",
+     "np.sqrt(l[:, 0] ** 2 + l[:, 1] ** 2 + l[:, 2] ** 2)"),
+    ("epipolar error measured at p", "np.sum(hom(q) * l, axis=1)", "np.sum(hom(p) * l, axis=1)"),
+    ("epipolar rank test dropped", "if len(sample) != 8 or sv[7] <= RANK_TOL * sv[0]:", "if len(sample) != 8:"),
+    ("epipolar ties to the highest index", "key=lambda i: (counts[i], -i)", "key=lambda i: (counts[i], i)"),
+]
+
+
+def run_planted(src_path, env_name, test_file):
+    env = dict(os.environ, **{env_name: src_path})
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", test_file],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+@pytest.mark.parametrize("name,old,new", EPI_MUTANTS, ids=[m[0] for m in EPI_MUTANTS])
+def test_epipolar_pins_catch_mutant(workdir, name, old, new):
+    text = open(EPI_SRC).read()
+    assert text.count(old) == 1, "mutation site not found: " + name
+    src = os.path.join(workdir, "epi_mut_%d.py" % (abs(hash(name)) % 10 ** 8))
+    open(src, "w").write(text.replace(old, new))
+    r = run_planted(src, "LKO_EPI_SRC", "tests/test_oracle_epipolar.py")
+    assert r.returncode != 0, "pins did not catch: " + name
+
+
+def test_unplanted_epipolar_copy_passes(workdir):
+    src = os.path.join(workdir, "epi_copy.py")
+    open(src, "w").write(open(EPI_SRC).read())
+    r = run_planted(src, "LKO_EPI_SRC", "tests/test_oracle_epipolar.py")
+    assert r.returncode == 0, r.stdout[-2000:]
+
 
 @pytest.mark.parametrize("name,old,new", POOL_MUTANTS, ids=[m[0] for m in POOL_MUTANTS])
 def test_pool_pins_catch_mutant(workdir, name, old, new):
