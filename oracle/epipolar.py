@@ -59,8 +59,9 @@ def errors(f, p, q):
 
 
 def check(p, q, samples, intr, threshold=1.0):
-    """Returns (best index or -1, inlier count of every hypothesis, inlier
-    mask of the best, per-hypothesis error arrays (None for no model))."""
+    """Returns (best index or -1, inlier count of every hypothesis (-1: no
+    model), inlier mask of the best, per-hypothesis error arrays (None for no
+    model))."""
     n = len(p)
     counts, errs = [], []
     for s in samples:
@@ -68,7 +69,7 @@ def check(p, q, samples, intr, threshold=1.0):
         ok = len(s) == 8 and all(0 <= i < n for i in s) and len(set(s)) == 8
         f = model(p, q, s, intr) if ok else None
         if f is None:
-            counts.append(0)
+            counts.append(-1)
             errs.append(None)
             continue
         e = errors(f, p, q)

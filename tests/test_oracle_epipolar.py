@@ -150,6 +150,6 @@ def test_degenerate_hypotheses_give_no_model():
     p2, q2 = two_views(40, R, t, seed=9)
     samples = [[0, 1, 2, 3, 4, 5, 6, 6], [0, 1, 2, 3, 4, 5, 6, 40], [0, 1, 2]]
     best, counts, mask, errs = E.check(p2, q2, samples, INTR)
-    assert best == -1 and counts.tolist() == [0, 0, 0] and not mask.any() and errs == [None, None, None]
+    assert best == -1 and counts.tolist() == [-1, -1, -1] and not mask.any() and errs == [None, None, None]
     best, counts, mask, _ = E.check(p2, q2, [], INTR)
     assert best == -1 and len(counts) == 0
