@@ -352,6 +352,44 @@ lk_result lk_pool_step(lk_pool *pool, const lk_pool_frame *h_frames, int32_t n_f
 lk_result lk_pool_reset(lk_pool *pool, lk_stream stream);
 lk_result lk_pool_destroy(lk_pool *pool);   /* waits for the device */
 
+/* ---- epipolar check (geometric verification after LK) ---------------------
+ * The paper verifies temporal correspondences geometrically: points are
+ * moved to the normalized image plane with the intrinsics, an essential
+ * matrix is estimated robustly and correspondences more than 1 px from their
+ * epipolar line are rejected (Sec. III-C).  Computed here as
+ * hypothesis-and-score over many sets (e.g. one per camera stream) at once:
+ *   1. hypothesis k of a set is 8 correspondences, indices given by the
+ *      caller (the random draws are inputs);
+ *   2. its model is the linear eight-point estimate: E with x_q^T E x_p = 0
+ *      for the 8 samples, x = K^-1 (u, v, 1), the null vector of the 8 x 9
+ *      system (binary64, elimination with complete pivoting); samples that
+ *      repeat an index or leave [0, n), or a system of numerical rank < 8
+ *      (a pivot below 1e-10 times the largest entry), give no model;
+ *   3. in pixels F = K^-T E K^-1; the error of correspondence i is the
+ *      distance of q_i to the epipolar line l = F (p_i, 1); it is an inlier
+ *      when that distance is at most threshold_px (binary64, decided as
+ *      (q.l)^2 <= t^2 (l1^2 + l2^2) with l1^2 + l2^2 > 0);
+ *   4. the best hypothesis has the most inliers (ties: the lowest index);
+ *      its inlier mask and model are written.
+ * Results are exact up to the rounding of the binary64 solve: a
+ * correspondence can flip only when its distance is within about 1e-9 px
+ * of the threshold. */
+typedef struct {
+    const float *p;          /* device, n x 2: positions in the earlier frame (pixels) */
+    const float *q;          /* device, n x 2: positions in the later frame */
+    int32_t n;               /* correspondences, >= 0 */
+    int32_t h;               /* hypotheses, >= 0 */
+    const int32_t *samples;  /* device, h x 8 indices into [0, n) */
+    float fx, fy, cx, cy;    /* intrinsics: focal lengths (> 0) and principal point, pixels */
+    int32_t *counts;         /* device, h: inliers of every hypothesis, -1 where there is no model */
+    uint8_t *inliers;        /* device, n: 1 for the inliers of the best hypothesis, else 0 (nullable if n == 0) */
+    int32_t *best;           /* device, 2: best hypothesis (-1: no model at all) and its inlier count */
+    double *model;           /* device, 9, nullable: the best F, row-major, unit Frobenius norm (zeros: none) */
+} lk_epi_set;
+
+lk_result lk_epipolar_check(lk_context *ctx, const lk_epi_set *h_sets, int32_t n_sets, double threshold_px,
+                            lk_stream stream);
+
 /* ---- serving (continuous batching over many camera streams) --------------
  * A server owns, per camera stream, device frame buffers and two resident
  * pyramids (the previous frame's and the current one's) plus pinned host

@@ -138,6 +138,20 @@ struct PoolJob {
     int32_t cap;                 // entries of every per-stream array
 };
 
+// One set of the epipolar check; its hypotheses are handled by the
+// workgroups [wg_begin, wg_begin + ceil(h / 64)) of the first launch.
+struct EpiJob {
+    const float *p, *q;
+    const int32_t *samples;
+    int32_t *counts;
+    uint8_t *inliers;
+    int32_t *best;
+    double *model;
+    double fx, fy, cx, cy;
+    int32_t n, h;
+    int32_t wg_begin, pad;
+};
+
 constexpr int kGfttTileW = 64, kGfttTileH = 16;
 constexpr int kGfttWindow = 2048;             // peaks sorted per selection window
 constexpr int kGfttMaxCorners = LK_GFTT_MAX_CORNERS;
@@ -191,6 +205,10 @@ hipError_t launch_pool_carry(const PoolJob *d_jobs, int n, hipStream_t stream);
 hipError_t launch_pool_append(const PoolJob *d_jobs, int n, hipStream_t stream);
 hipError_t launch_pool_commit(const PoolJob *d_jobs, int n, hipStream_t stream);
 hipError_t launch_pool_reset(int32_t *d_count, int64_t *d_next_id, int n, hipStream_t stream);
+// Epipolar check of every set (lk_epipolar_kernels.hip): hypotheses, then
+// the best of each set.  d_wg_job[b] is the set of workgroup b.
+hipError_t launch_epipolar(const EpiJob *d_jobs, const int32_t *d_wg_job, int n_jobs, int total_wgs, double threshold,
+                           hipStream_t stream);
 hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream);
 
 }  // namespace lkmi

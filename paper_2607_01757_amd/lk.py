@@ -30,6 +30,7 @@ ABI_SYMBOLS = (
     "lk_server_get_stats", "lk_server_destroy",
     "lk_detector_create", "lk_detect_corners", "lk_detector_destroy",
     "lk_pool_create", "lk_pool_step", "lk_pool_reset", "lk_pool_destroy",
+    "lk_epipolar_check",
 )
 LK_GFTT_MAX_CORNERS = 4096
 
@@ -100,6 +101,12 @@ class lk_pool_frame(C.Structure):
                 ("right", C.c_void_p)]
 
 
+class lk_epi_set(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("q", C.c_void_p), ("n", C.c_int32), ("h", C.c_int32), ("samples", C.c_void_p),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float), ("counts", C.c_void_p),
+                ("inliers", C.c_void_p), ("best", C.c_void_p), ("model", C.c_void_p)]
+
+
 class LKError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("lk error %d: %s" % (code, msg))
@@ -148,6 +155,7 @@ def _load():
                                C.POINTER(lk_gftt_params), vp]),
         "lk_pool_reset": (res, [vp, vp]),
         "lk_pool_destroy": (res, [vp]),
+        "lk_epipolar_check": (res, [vp, C.POINTER(lk_epi_set), i32, C.c_double, vp]),
     }
     for name, (rt, at) in sig.items():
         f = getattr(lib, name)
@@ -410,6 +418,19 @@ def lk_pool_reset(pool, stream=None):
 
 def lk_pool_destroy(pool):
     _check(lib.lk_pool_destroy(pool))
+
+
+def lk_epipolar_check(ctx, sets, threshold_px: float = 1.0, stream=None):
+    """sets: sequence of dicts with p, q (float32 CUDA tensors, n x 2),
+    samples (int32 CUDA tensor, h x 8), intr (fx, fy, cx, cy), counts (int32,
+    h), inliers (uint8, n), best (int32, 2) and optionally model (float64, 9)."""
+    n = len(sets)
+    S = (lk_epi_set * max(n, 1))()
+    for i, d in enumerate(sets):
+        fx, fy, cx, cy = d["intr"]
+        S[i] = lk_epi_set(_ptr(d["p"]), _ptr(d["q"]), d["p"].shape[0], d["samples"].shape[0], _ptr(d["samples"]),
+                          fx, fy, cx, cy, _ptr(d["counts"]), _ptr(d["inliers"]), _ptr(d["best"]), _ptr(d.get("model")))
+    _check(lib.lk_epipolar_check(ctx, S, n, threshold_px, _stream(stream)))
 
 
 # ---------------------------------------------------------------- helpers

@@ -3,4 +3,4 @@ tests, the benchmark and the oracle checks; contains none of the tracker's
 arithmetic."""
 from .texture import make_rng, quantize_u8, texture_canvas  # noqa: F401
 from .workloads import (RESOLUTIONS, FramePool, Pair, ServingTrace,  # noqa: F401
-                        StereoSequence, batch_streams, pair, uniform_points)
+                        StereoSequence, TwoView, batch_streams, pair, ransac_samples, two_view, uniform_points)

@@ -258,3 +258,54 @@ class FramePool:
     def frame(self, width: int, height: int, stream: int, k: int) -> np.ndarray:
         lst = self.frames[(width, height)]
         return lst[(stream + k) % len(lst)]
+
+
+# --------------------------------------------------------------------------
+# Two-view correspondences for the epipolar check
+# --------------------------------------------------------------------------
+
+@dataclass
+class TwoView:
+    p: np.ndarray          # (n, 2) float32, earlier frame (pixels)
+    q: np.ndarray          # (n, 2) float32, later frame
+    intr: tuple            # (fx, fy, cx, cy)
+    outlier: np.ndarray    # (n,) bool: q replaced by a point off its epipolar line
+
+
+def _rot(ax, ay, az):
+    cx, sx, cy, sy, cz, sz = np.cos(ax), np.sin(ax), np.cos(ay), np.sin(ay), np.cos(az), np.sin(az)
+    return (np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]]) @ np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+            @ np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]]))
+
+
+def two_view(seed: int, n: int, width: int = 752, height: int = 480, outlier_frac: float = 0.2,
+             noise_px: float = 0.3, forward: bool = False) -> TwoView:
+    """Points of a 3D scene (depth 4..20 units, in front of both cameras)
+    seen by a camera and by the same camera after a small rotation and a
+    translation (sideways, or along the axis with `forward`), projected with
+    pinhole intrinsics, Gaussian pixel noise on both views; a fraction of the
+    later positions is replaced by uniform random pixels (outliers)."""
+    rng = make_rng(0xE9, seed)
+    f = 0.6 * width
+    intr = (f, f * rng.uniform(0.98, 1.02), width / 2.0 + rng.uniform(-8, 8), height / 2.0 + rng.uniform(-8, 8))
+    K = np.array([[intr[0], 0, intr[2]], [0, intr[1], intr[3]], [0, 0, 1.0]])
+    R = _rot(*rng.uniform(-0.03, 0.03, 3))
+    t = np.array([0.0, 0.0, 1.0]) if forward else np.concatenate([rng.uniform(-0.5, 0.5, 2), rng.uniform(-0.1, 0.1, 1)])
+    # pixels of the earlier view with random depths, lifted to 3D
+    u = np.column_stack([rng.uniform(0, width - 1, n), rng.uniform(0, height - 1, n), np.ones(n)])
+    X = (np.linalg.inv(K) @ u.T).T * rng.uniform(4.0, 20.0, (n, 1))
+    X2 = (R @ X.T).T + t
+    x2 = (K @ X2.T).T
+    p = u[:, :2] + rng.normal(0.0, noise_px, (n, 2))
+    q = x2[:, :2] / x2[:, 2:] + rng.normal(0.0, noise_px, (n, 2))
+    out = rng.random(n) < outlier_frac
+    q[out] = np.column_stack([rng.uniform(0, width - 1, out.sum()), rng.uniform(0, height - 1, out.sum())])
+    return TwoView(p.astype(np.float32), q.astype(np.float32), tuple(float(v) for v in intr), out)
+
+
+def ransac_samples(seed: int, n: int, h: int, k: int = 8) -> np.ndarray:
+    """h draws of k distinct indices in [0, n) (int32, h x k)."""
+    rng = make_rng(0xE8, seed)
+    if n < k:
+        return np.zeros((h, k), np.int32)
+    return np.stack([rng.choice(n, k, replace=False) for _ in range(h)]).astype(np.int32).reshape(h, k)

@@ -25,6 +25,7 @@ STRUCTS = {
     "lk_pool_state": ["pts", "ids", "right", "count", "next_id", "stats"],
     "lk_pool_scratch": ["t_pts", "t_status", "c_pts", "c_ids", "c_count", "s_pts", "s_status"],
     "lk_pool_frame": ["stream", "reserved", "prev", "next", "right"],
+    "lk_epi_set": ["p", "q", "n", "h", "samples", "fx", "fy", "cx", "cy", "counts", "inliers", "best", "model"],
 }
 
 
