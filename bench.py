@@ -840,6 +840,65 @@ def run_frontend(args):
     return result
 
 
+def run_epipolar(args):
+    """Epipolar check after LK (the geometric verification of temporal
+    correspondences): 64 sets (one per camera stream) of 256 correspondences
+    (the paper's keypoint cap), 512 eight-point hypotheses each, 1 px
+    threshold, in one call."""
+    import torch
+    import synth
+    import oracle.epipolar as E_or
+    from paper_2607_01757_amd import lk
+
+    n_sets, n, h = args.streams, args.epi_points, args.epi_hypotheses
+    views = [synth.two_view(args.seed * 1000 + k, n, forward=(k % 4 == 0)) for k in range(n_sets)]
+    samples = [synth.ransac_samples(args.seed * 1000 + k, n, h) for k in range(n_sets)]
+    sets = []
+    for tv, smp in zip(views, samples):
+        sets.append({"p": torch.from_numpy(tv.p).cuda(), "q": torch.from_numpy(tv.q).cuda(),
+                     "samples": torch.from_numpy(smp).cuda(), "intr": tv.intr,
+                     "counts": torch.empty((h,), dtype=torch.int32, device="cuda"),
+                     "inliers": torch.empty((n,), dtype=torch.uint8, device="cuda"),
+                     "best": torch.empty((2,), dtype=torch.int32, device="cuda"),
+                     "model": torch.empty((9,), dtype=torch.float64, device="cuda")})
+    ctx = lk.lk_context_create(0, 0)
+    wall, per = time_steps(lambda: lk.lk_epipolar_check(ctx, sets, 1.0), args.steps, args.warmup)
+    t = time_block(lambda: lk.lk_epipolar_check(ctx, sets, 1.0), max(args.steps, 10), args.warmup)
+    got = [int(d["best"][1].item()) for d in sets]
+    truth = [int((~tv.outlier).sum()) for tv in views]
+    # algorithmic binary64 flops: per hypothesis the elimination of the 8 x 9
+    # system (sum over pivots of 2 (8-k)(9-k) plus back substitution, ~580),
+    # the pixel-space model (~60), and 21 per scored correspondence
+    flops = n_sets * h * (640 + 21 * n)
+    step = wall / args.steps
+    result = {
+        "metric": "epipolar checks/sec (batched, 64 sets of 256 correspondences x 512 hypotheses)",
+        "value": n_sets / step, "unit": "sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "epipolar: %d sets of %d two-view correspondences (20%% outliers, 0.3 px noise, every "
+                               "4th set forward motion), %d eight-point hypotheses each, 1 px threshold" % (
+                                   n_sets, n, h)},
+        "p50_step_ms": percentile(per, 50), "p99_step_ms": percentile(per, 99),
+        "hypothesis_scores_per_s": n_sets * h * n / t,
+        "inliers_found_vs_planted": float(np.mean(np.array(got) / np.array(truth))),
+        "roofline": {"bound": "alu", "kernel": "k_epi_hypotheses+k_epi_best", "achieved": flops / t / 1e12,
+                     "peak": 78.6, "unit": "TFLOP/s (fp64 vector)", "frac": flops / t / 1e12 / 78.6, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        k = min(n_sets, 64)
+        t0 = time.perf_counter()
+        for tv, smp in list(zip(views, samples))[:k]:
+            E_or.check(tv.p, tv.q, smp, tv.intr, 1.0)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": k / dt, "unit": "sets/s", "cores": 1, "kind": "oracle",
+                                  "sample": "first %d of the %d sets, numpy on one thread, %.1f s" % (k, n_sets, dt)}
+    log("epipolar: %.3f ms per call (%d sets), %.3g sets/s, best inliers / planted %.3f" %
+        (step * 1e3, n_sets, n_sets / step, result["inliers_found_vs_planted"]))
+    lk.lk_context_destroy(ctx)
+    return result
+
+
 SWEEP_KP = (160, 192, 256, 384, 512, 768, 1000, 1500)
 
 
@@ -945,7 +1004,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "pair", "stereo", "stereo16", "serve",
-                                                           "detect", "sweep", "frontend", "copy"])
+                                                           "detect", "sweep", "frontend", "epipolar", "copy"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--precision-frames", type=int, default=5)
     ap.add_argument("--serve-streams", type=int, default=256)
@@ -960,6 +1019,8 @@ def main():
     ap.add_argument("--gftt-corners", type=int, default=200)
     ap.add_argument("--pool-cap", type=int, default=256, help="tracks per stream (frontend workload)")
     ap.add_argument("--mono", action="store_true", help="frontend workload without the cross-camera gate")
+    ap.add_argument("--epi-points", type=int, default=256, help="correspondences per set (epipolar workload)")
+    ap.add_argument("--epi-hypotheses", type=int, default=512, help="hypotheses per set (epipolar workload)")
     ap.add_argument("--storage", choices=["f32", "f16"], default="f32",
                     help="pyramid storage of the batched workload")
     args = ap.parse_args()
@@ -977,6 +1038,8 @@ def main():
         res = run_sweep(args)
     elif args.workload == "frontend":
         res = run_frontend(args)
+    elif args.workload == "epipolar":
+        res = run_epipolar(args)
     elif args.workload == "pair":
         res = run_pair(args)
     elif args.workload in ("stereo", "stereo16"):
