@@ -988,7 +988,6 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         return pr;
     }
     float T[R][CW], GX[R][CW], GY[R][CW];
-    float jt[R + 1][CW + 1];
     float dx = 0.0f, dy = 0.0f;
     float cfx = 0.0f, cfy = 0.0f;
     int cix = 0, ciy = 0;
@@ -1056,18 +1055,19 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         const Plane PJ = l == 0 ? make_plane<K_U8>(LJ.img, LJ.pitch, LJ.w, LJ.h)
                                 : (ST == LK_STORAGE_F16 ? make_plane<K_F16>(LJ.img, LJ.pitch, LJ.w, LJ.h)
                                                         : make_plane<K_F32>(LJ.img, LJ.pitch, LJ.w, LJ.h));
+        // target taps of this level: loaded at the first iteration and
+        // whenever the integer part of the estimate moves
+        float jt[R + 1][CW + 1];
         int jbx = INT_MIN, jby = INT_MIN;
         dx = 0.0f; dy = 0.0f;
         int k = 0;
+        bool oob = false;
         while (k < a.max_iters) {
             ++k;
             const float ux = (cfx + gx) + dx, uy = (cfy + gy) + dy;
             if (!(ux >= lox && ux <= hix && uy >= loy && uy <= hiy)) {
-                pr.status = LK_LOST_OOB;
-                pr.ox = ldexpf((float)cix + ux, l);
-                pr.oy = ldexpf((float)ciy + uy, l);
-                if (iters && lc.lane0) iters[l] = k - 1;
-                return pr;
+                oob = true;          // the window left the level before this step
+                break;
             }
             const float fux = floorf(ux), fuy = floorf(uy);
             const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
@@ -1096,6 +1096,14 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             dy += ey;
             if (ex * ex + ey * ey < eps2) break;
         }
+        if (oob) {
+            const float ux = (cfx + gx) + dx, uy = (cfy + gy) + dy;
+            pr.status = LK_LOST_OOB;
+            pr.ox = ldexpf((float)cix + ux, l);
+            pr.oy = ldexpf((float)ciy + uy, l);
+            if (iters && lc.lane0) iters[l] = k - 1;
+            return pr;
+        }
         if (iters && lc.lane0) iters[l] = k;
         if (l > 0) {
             gx = 2.0f * (gx + dx);
@@ -1117,6 +1125,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         const float fuy = fminf(fmaxf(floorf(uy), (float)(-ciy - h - 2)), (float)(LJ.h + h + 2 - ciy));
         const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
         const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
+        float jt[R + 1][CW + 1];
         load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
         const Weights w = bilinear_weights(ux - fux, uy - fuy);
         float acc = 0.0f;
