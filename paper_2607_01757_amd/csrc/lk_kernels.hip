@@ -1039,16 +1039,21 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         const double ddet = (double)Gxx * (double)Gyy - (double)Gxy * (double)Gxy;
         const float det = (float)ddet;
         {
-            const float lmax = 0.5f * ((Gxx + Gyy) + sqrtf((Gxx - Gyy) * (Gxx - Gyy) + 4.0f * Gxy * Gxy));
-            const float meig = det / lmax / (nw * 65025.0f);
-            if (!(meig >= a.min_eig)) {
+            // lambda_min / (N_w 255^2) >= min_eig, as det >= min_eig N_w 255^2
+            // lambda_max with lambda_max > 0 (a flat window, lambda_max = 0, and
+            // NaN fail); the uniform scalar work runs on the vector ALU, so the
+            // hardware square root (1 ulp) replaces the refined one and no
+            // division is needed
+            const float lmax =
+                0.5f * ((Gxx + Gyy) + __builtin_amdgcn_sqrtf((Gxx - Gyy) * (Gxx - Gyy) + 4.0f * Gxy * Gxy));
+            if (!(lmax > 0.0f && det >= a.min_eig * (nw * 65025.0f) * lmax)) {
                 pr.status = LK_LOST_EIG;
                 pr.ox = ldexpf((float)cix + (cfx + gx), l);
                 pr.oy = ldexpf((float)ciy + (cfy + gy), l);
                 return pr;
             }
         }
-        const float rdet = 1.0f / det;
+        const float rdet = __builtin_amdgcn_rcpf(det);      // 1 ulp
         const float lox = (float)(-h - cix), hix = (float)(LJ.w - 1 + h - cix);
         const float loy = (float)(-h - ciy), hiy = (float)(LJ.h - 1 + h - ciy);
         const float eps2 = a.eps * a.eps;
