@@ -13,7 +13,8 @@
 //                  are formed there, every in-frame 3x3 local maximum with
 //                  R > 0 is appended to the frame's peak list and the frame
 //                  maximum is raised with one atomic per workgroup;
-//   k_gftt_compact keeps the peaks above the quality threshold;
+//   k_gftt_compact keeps the peaks above the quality threshold that no cached
+//                  occupied point blocks;
 //   k_gftt_select  one workgroup per frame: the quality threshold follows
 //                  from the maximum; windows of the best remaining peaks are
 //                  found by radix selection on the 96-bit rank key (R bits,
@@ -216,12 +217,137 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
 // candidates by the total rank key.
 constexpr int kCompactBlocks = 32;
 
-__global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restrict__ jobs, double quality)
+// ---- occupied points ----------------------------------------------------------
+//
+// The first OCC_LDS occupied points of a frame, grouped by the cells of a grid
+// of cs x cs pixels with cs >= min_dist (at most OCC_GRID cells): a point
+// closer than min_dist to an integer pixel lies in that pixel's cell or one of
+// its 8 neighbours (points off the frame, or not finite, go to the nearest
+// border cell, where they are still checked and never match), so a pixel
+// checks only those 9 cells, with the binary64 distance rule of the selection.
+
+constexpr int OCC_LDS = 1024;                 // occupied points cached in LDS
+constexpr int OCC_GRID = 4096;                // cells of their grid
+
+struct OccGridSmem {
+    float2 occ[OCC_LDS];                       // the cached points, grouped by cell
+    uint32_t end[OCC_GRID];                    // end of each cell's group in occ
+    uint32_t wsum[16];
+};
+
+struct OccGrid {
+    int cs, gx, gy, nl;
+};
+
+// Built by all NT threads of the workgroup; ends with a barrier.
+template <int NT>
+__device__ OccGrid occ_grid_build(const GfttJob &J, int n_occ, int min_dist, OccGridSmem &g)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    OccGrid G;
+    G.nl = n_occ < OCC_LDS ? n_occ : OCC_LDS;
+    G.cs = min_dist > 1 ? min_dist : 1;
+    for (;;) {
+        G.gx = (J.w + G.cs - 1) / G.cs;
+        G.gy = (J.h + G.cs - 1) / G.cs;
+        if (G.gx * G.gy <= OCC_GRID) break;
+        G.cs += (G.cs >> 2) + 1;
+    }
+    const int ncell = G.gx * G.gy;
+    auto cell_of = [&](float ox, float oy) {
+        const float lim = (float)(2 * G.cs);
+        const int ix = (int)floorf(fminf(fmaxf(ox, -lim), (float)J.w + lim));
+        const int iy = (int)floorf(fminf(fmaxf(oy, -lim), (float)J.h + lim));
+        const int cx = ix < 0 ? 0 : min(ix / G.cs, G.gx - 1), cy = iy < 0 ? 0 : min(iy / G.cs, G.gy - 1);
+        return cy * G.gx + cx;
+    };
+    if (G.nl > 0) {
+        for (int k = tid; k < ncell; k += NT) g.end[k] = 0;
+        __syncthreads();
+        for (int k = tid; k < G.nl; k += NT) atomicAdd(&g.end[cell_of(J.occupied[2 * k], J.occupied[2 * k + 1])], 1u);
+        __syncthreads();
+        // exclusive prefix sum over the cells, PER consecutive cells per thread
+        constexpr int PER = OCC_GRID / NT;
+        uint32_t v[PER], tsum = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = tid * PER + i;
+            v[i] = c < ncell ? g.end[c] : 0u;
+            tsum += v[i];
+        }
+        uint32_t incl = tsum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) g.wsum[wv] = incl;
+        __syncthreads();
+        uint32_t run = incl - tsum;
+        for (int w = 0; w < wv; ++w) run += g.wsum[w];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = tid * PER + i;
+            if (c < ncell) g.end[c] = run;
+            run += v[i];
+        }
+        __syncthreads();
+        // scatter: each cell's counter ends at the end of its group
+        for (int k = tid; k < G.nl; k += NT) {
+            const float ox = J.occupied[2 * k], oy = J.occupied[2 * k + 1];
+            const uint32_t at = atomicAdd(&g.end[cell_of(ox, oy)], 1u);
+            g.occ[at] = make_float2(ox, oy);
+        }
+    }
+    __syncthreads();
+    return G;
+}
+
+// Some cached occupied point lies at binary64 squared distance < md2d from
+// the integer pixel (x, y).
+__device__ __forceinline__ bool occ_grid_blocked(const OccGrid &G, const OccGridSmem &g, int x, int y, double md2d)
+{
+    bool blocked = false;
+    const int ccx = x / G.cs, ccy = y / G.cs;
+    for (int yy = max(ccy - 1, 0); yy <= min(ccy + 1, G.gy - 1) && !blocked; ++yy) {
+        const int c0 = yy * G.gx + max(ccx - 1, 0), c1 = yy * G.gx + min(ccx + 1, G.gx - 1);
+        // the three cells of a row are consecutive groups
+        const int b = c0 == 0 ? 0 : (int)g.end[c0 - 1], e = (int)g.end[c1];
+        for (int q = b; q < e && !blocked; ++q) {
+            const float2 o = g.occ[q];
+            double dd;
+            {
+#pragma clang fp contract(off)
+                const double dx = (double)x - (double)o.x, dy = (double)y - (double)o.y;
+                dd = dx * dx + dy * dy;
+            }
+            blocked |= dd < md2d;
+        }
+    }
+    return blocked;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restrict__ jobs, double quality,
+                                                       int min_dist)
 {
     __shared__ uint32_t s_cnt[BLOCK / 64], s_base;
+    __shared__ OccGridSmem s_grid;
     const GfttJob &J = jobs[blockIdx.y];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int np = *J.n_peaks;
+    // peaks that a cached occupied point blocks can never be selected: they
+    // are dropped here (the selection still checks every occupied point)
+    const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
+    const bool filter = n_occ > 0 && min_dist > 0;
+    OccGrid G{1, 1, 1, 0};
+    if (filter) G = occ_grid_build<BLOCK>(J, n_occ, min_dist, s_grid);
+    const double md2d = (double)min_dist * (double)min_dist;
+    const int W = J.w;
+    auto kept = [&](const GfttPeak &p) {
+        if (!filter) return true;
+        const int y = (int)(p.idx / (uint32_t)W), x = (int)p.idx - y * W;
+        return !occ_grid_blocked(G, s_grid, x, y, md2d);
+    };
     const double thr = quality * __longlong_as_double((long long)*J.max_bits);
     const unsigned long long thr_bits = (unsigned long long)__double_as_longlong(thr);
     // this workgroup's slice of the frame's peaks, in steps of BLOCK
@@ -230,7 +356,10 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
     uint32_t mine = 0;
     for (int k0 = k_lo; k0 < k_hi; k0 += BLOCK) {
         const int k = k0 + threadIdx.x;
-        mine += (k < k_hi && J.peaks[k].rbits > thr_bits) ? 1u : 0u;
+        if (k < k_hi) {
+            const GfttPeak p = J.peaks[k];
+            mine += (p.rbits > thr_bits && kept(p)) ? 1u : 0u;
+        }
     }
     // wavefront and workgroup totals, one global atomic
     uint32_t wsum = mine;
@@ -252,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
         bool keep = false;
         if (k < k_hi) {
             p = J.peaks[k];
-            keep = p.rbits > thr_bits;
+            keep = p.rbits > thr_bits && kept(p);
         }
         const unsigned long long m = __ballot(keep);
         uint32_t wc = (uint32_t)__popcll(m);
@@ -276,9 +405,6 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
 constexpr int CAPW = kGfttWindow;             // window of peaks sorted in LDS
 constexpr int SBLOCK = 512;                   // threads of the selection workgroup
 constexpr int CHUNK = SBLOCK;                 // candidates decided together
-constexpr int OCC_LDS = 1024;                 // occupied points cached in LDS
-constexpr int OCC_GRID = 4096;                // cells of their grid
-
 struct Key {
     unsigned long long hi;   // bits of R (R > 0, so the bits order like R)
     uint32_t lo;             // complemented raster index: larger = earlier
@@ -322,9 +448,7 @@ struct alignas(16) SelSmem {
     unsigned long long whi[CAPW];
     uint32_t wlo[CAPW];
     uint32_t taken[kGfttMaxCorners + 16];     // x | y << 16
-    float2 occ[OCC_LDS];                       // the cached occupied points, grouped by grid cell
-    uint32_t occ_end[OCC_GRID];                // end of each cell's group in occ
-    uint32_t wsum[SBLOCK / 64];
+    OccGridSmem grid;                          // the cached occupied points
     int32_t cx[CHUNK], cy[CHUNK];
     uint32_t hist[SBLOCK / 64][256];           // one histogram per wavefront
     unsigned long long cmask[CHUNK][CHUNK / 64];   // conflicts with better candidates of the chunk
@@ -369,65 +493,7 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     const GfttPeak *cand = J.cand;
     const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
 
-    // The first OCC_LDS occupied points, grouped by the cells of a grid of
-    // cs x cs pixels with cs >= min_dist: a point closer than min_dist to an
-    // integer pixel lies in that pixel's cell or one of its 8 neighbours
-    // (points off the frame, or not finite, go to the nearest border cell),
-    // so a candidate checks only those 9 cells, with the same binary64 rule.
-    const int nl = n_occ < OCC_LDS ? n_occ : OCC_LDS;
-    int cs = min_dist > 1 ? min_dist : 1, gx, gy;
-    for (;;) {
-        gx = (W + cs - 1) / cs;
-        gy = (J.h + cs - 1) / cs;
-        if (gx * gy <= OCC_GRID) break;
-        cs += (cs >> 2) + 1;
-    }
-    const int ncell = gx * gy;
-    auto cell_of = [&](float ox, float oy) {
-        const float lim = (float)(2 * cs);
-        const int ix = (int)floorf(fminf(fmaxf(ox, -lim), (float)W + lim));
-        const int iy = (int)floorf(fminf(fmaxf(oy, -lim), (float)J.h + lim));
-        const int cx = ix < 0 ? 0 : min(ix / cs, gx - 1), cy = iy < 0 ? 0 : min(iy / cs, gy - 1);
-        return cy * gx + cx;
-    };
-    if (nl > 0) {
-        for (int k = tid; k < ncell; k += SBLOCK) sm.occ_end[k] = 0;
-        __syncthreads();
-        for (int k = tid; k < nl; k += SBLOCK) atomicAdd(&sm.occ_end[cell_of(J.occupied[2 * k], J.occupied[2 * k + 1])], 1u);
-        __syncthreads();
-        // exclusive prefix sum over the cells, 8 per thread
-        constexpr int PER = OCC_GRID / SBLOCK;
-        uint32_t v[PER], tsum = 0;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int c = tid * PER + i;
-            v[i] = c < ncell ? sm.occ_end[c] : 0u;
-            tsum += v[i];
-        }
-        uint32_t incl = tsum;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += t;
-        }
-        if (lane == 63) sm.wsum[wv] = incl;
-        __syncthreads();
-        uint32_t run = incl - tsum;
-        for (int w = 0; w < wv; ++w) run += sm.wsum[w];
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int c = tid * PER + i;
-            if (c < ncell) sm.occ_end[c] = run;
-            run += v[i];
-        }
-        __syncthreads();
-        // scatter: each cell's counter ends at the end of its group
-        for (int k = tid; k < nl; k += SBLOCK) {
-            const float ox = J.occupied[2 * k], oy = J.occupied[2 * k + 1];
-            const uint32_t at = atomicAdd(&sm.occ_end[cell_of(ox, oy)], 1u);
-            sm.occ[at] = make_float2(ox, oy);
-        }
-    }
+    const OccGrid G = occ_grid_build<SBLOCK>(J, n_occ, min_dist, sm.grid);
     int remaining = np;
     int nt = 0;
     bool bounded = false;
@@ -573,24 +639,9 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                     }
                 }
             }
-            // occupied points, 8 per step (binary64 distance)
+            // occupied points (binary64 distance): the grid, then any beyond the cache
             if (valid && n_occ > 0) {
-                const int ccx = x / cs, ccy = y / cs;
-                for (int yy = max(ccy - 1, 0); yy <= min(ccy + 1, gy - 1) && !blocked; ++yy) {
-                    const int c0 = yy * gx + max(ccx - 1, 0), c1 = yy * gx + min(ccx + 1, gx - 1);
-                    // the three cells of a row are consecutive groups
-                    const int b = c0 == 0 ? 0 : (int)sm.occ_end[c0 - 1], e = (int)sm.occ_end[c1];
-                    for (int q = b; q < e && !blocked; ++q) {
-                        const float2 o = sm.occ[q];
-                        double dd;
-                        {
-#pragma clang fp contract(off)
-                            const double dx = (double)x - (double)o.x, dy = (double)y - (double)o.y;
-                            dd = dx * dx + dy * dy;
-                        }
-                        blocked |= dd < md2d;
-                    }
-                }
+                blocked = blocked || occ_grid_blocked(G, sm.grid, x, y, md2d);
                 for (int q = OCC_LDS; q < n_occ && !blocked; ++q) {
                     double dd;
                     {
@@ -717,7 +768,7 @@ hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njo
     case 2: k_gftt_peaks<2><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     default: k_gftt_peaks<3><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     }
-    k_gftt_compact<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality);
+    k_gftt_compact<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality, min_dist);
     k_gftt_select<<<njobs, SBLOCK, 0, s>>>(d_jobs, min_dist, max_corners);
     return hipGetLastError();
 }
