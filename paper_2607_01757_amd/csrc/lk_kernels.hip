@@ -596,8 +596,11 @@ struct Geo {
     static constexpr int TBW = EXX + 2, TBH = EXY + 2;         // interpolated template incl. a one-pixel halo
     // LDS row strides of the tap region and of the interpolated template,
     // chosen so that the lane segments of a wavefront (rows r0 = 0, R, 2R)
-    // fall on disjoint banks whether the LDS has 32 or 64 banks: for 7-row
-    // segments 7 x 67 = 21 (mod 64), for 16-row segments 16 x 34 = 32 (mod 64)
+    // fall on disjoint banks: the LDS serves a wavefront as two halves of 32
+    // lanes over 32 banks, and 7 x 67 = 21, 14 x 67 = 10 (mod 32) put the
+    // 21-lane segments of the 1x7 layout on banks 0-20 and 21-31 (first half),
+    // 0-9 and 10-30 (second half); 16 x 34 = 0 (mod 32) with 31-lane segments
+    // gives one segment per half for the 1x16 layout
     static constexpr int RS = CW == 1 && R == 7 ? 67 : (CW == 1 && R == 16 ? 34 : (TW | 1));
     static constexpr int TBS = RS > TBW ? RS : (TBW | 1);
     static constexpr int LDS_OLD = SW * SH + 2 * TW * TH;      // staged level + two gradient planes
@@ -624,7 +627,10 @@ __device__ __forceinline__ LaneCfg lane_cfg(int win, int lane)
     const int ncg = (win + G::CW - 1) / G::CW, nsg = (win + G::R - 1) / G::R;
     LaneCfg c;
     c.active = lane < ncg * nsg;
-    const int cg = c.active ? lane % ncg : 0, sg = c.active ? lane / ncg : 0;
+    // an inactive lane takes the geometry of an active lane of its own
+    // 32-lane half where there is one (same LDS addresses: no bank conflict)
+    const int src = c.active ? lane : ((lane & 31) < ncg * nsg ? (lane & 31) : 0);
+    const int cg = src % ncg, sg = src / ncg;
     c.c0 = cg * G::CW;
     c.r0 = sg * G::R;
     c.lane0 = lane == 0;
@@ -821,6 +827,20 @@ __device__ __forceinline__ float bload_at(const Plane &p, int voff, int soff)
     else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs, voff, soff, 0));
 }
 
+// Row group g and column c of a lane when NG groups of RW lanes lie side by
+// side.  The LDS serves a wavefront as two halves of 32 lanes over 32 banks;
+// an idle lane (past the groups) repeats an active lane of its own half, so
+// its accesses hit the same addresses (a broadcast) and add no conflicts.
+template <int RW, int NG>
+__device__ __forceinline__ void group_lane(int lane, int &g, int &c)
+{
+    constexpr int ACT = NG * RW;
+    int l = lane;
+    if (lane >= ACT) l = ACT > 32 ? 32 + (lane - ACT) % (ACT - 32) : lane % ACT;
+    g = l / RW;
+    c = l - g * RW;
+}
+
 // The rectangle [x0, x0 + RW) x [y0, y0 + RH) of a level into wave-private
 // LDS, dense with row stride RW.  Lanes are (row group, column): each load
 // instruction fills rows of the rectangle, its row offset a scalar.  Lanes
@@ -841,9 +861,7 @@ __device__ __forceinline__ void load_rect(const Plane &P, int x0, int y0, bool i
     for (int cp = 0; cp < CP; ++cp) {
         int g, c;
         if constexpr (RW <= 64) {
-            g = lane / RW;
-            c = lane - g * RW;
-            if (g >= NG) { g = 0; }                       // idle lanes repeat group 0
+            group_lane<RW, NG>(lane, g, c);
         } else {
             g = 0;
             c = min(lane + 64 * cp, RW - 1);              // the last pass repeats the last column
@@ -909,9 +927,8 @@ __device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_
         // another lane writes (same value), so nothing is predicated
         constexpr int NG = 64 / TBW, KS = (TBH + NG - 1) / NG;
         constexpr bool RAGGED = KS * NG != TBH;
-        int g = lane / TBW;
-        const int b = lane - g * TBW;
-        if (g >= NG) g = 0;
+        int g, b;
+        group_lane<TBW, NG>(lane, g, b);
         constexpr int KB = KS <= 12 ? KS : 8;
 #pragma unroll 1
         for (int k0 = 0; k0 < KS; k0 += KB) {
