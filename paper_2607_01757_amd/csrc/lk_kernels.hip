@@ -536,15 +536,38 @@ __device__ __forceinline__ T *uniform_ptr(T *p)
 // Level descriptor read from memory, made provably wave-uniform (the
 // descriptor is the same for the whole wavefront), so that buffer resources
 // built from it live in scalar registers.
+// Descriptors and batch tables are written before a kernel that reads them
+// starts and never while it runs, at wave-uniform addresses: they are read
+// through the constant address space, i.e. with scalar loads.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_constant(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)(uintptr_t)p;
+}
+
+__device__ __forceinline__ BatchItem load_item(const BatchItem *items, int i)
+{
+    const auto *q = as_constant(items) + i;
+    BatchItem it;
+    it.prev = q->prev;
+    it.next = q->next;
+    it.pt_offset = q->pt_offset;
+    it.n = q->n;
+    it.first_wave = q->first_wave;
+    it.limit = q->limit;
+    return it;
+}
+
 __device__ __forceinline__ LevelDesc uniform_level(const LevelDesc &d)
 {
+    const auto *q = as_constant(&d);
     LevelDesc u;
-    u.img = uniform_ptr(d.img);
-    u.grad = uniform_ptr(d.grad);
-    u.pitch = uniform_i(d.pitch);
-    u.gpitch = uniform_i(d.gpitch);
-    u.w = uniform_i(d.w);
-    u.h = uniform_i(d.h);
+    u.img = q->img;
+    u.grad = q->grad;
+    u.pitch = q->pitch;
+    u.gpitch = q->gpitch;
+    u.w = q->w;
+    u.h = q->h;
     return u;
 }
 
@@ -999,7 +1022,8 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
     PassResult pr;
     pr.status = LK_OK;
     pr.ox = px; pr.oy = py; pr.fx = 0.0f; pr.fy = 0.0f; pr.res = 0.0f;
-    const int w0 = uniform_i(I.lv[0].w), h0 = uniform_i(I.lv[0].h);
+    const LevelDesc L0 = uniform_level(I.lv[0]);
+    const int w0 = L0.w, h0 = L0.h;
     if (!(px >= 0.0f && px <= (float)(w0 - 1) && py >= 0.0f && py <= (float)(h0 - 1))) {
         pr.status = LK_LOST_OOB;
         return pr;
@@ -1227,11 +1251,11 @@ void k_track_batched(const BatchItem *items, int n_items, TrackArgs a)
     int lo = 0, hi = n_items - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].first_wave <= wave) lo = mid; else hi = mid - 1;
+        if (as_constant(items)[mid].first_wave <= wave) lo = mid; else hi = mid - 1;
     }
     lo = uniform_i(lo);
-    const BatchItem &it = items[lo];
-    if (it.limit && wave - it.first_wave >= *it.limit) return;      // past the item's live count
+    const BatchItem it = load_item(items, lo);
+    if (it.limit && wave - it.first_wave >= *as_constant(it.limit)) return;   // past the item's live count
     const int idx = (int)(it.pt_offset + (wave - it.first_wave));
     track_point<ST, G>(*it.prev, *it.next, a, idx, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
 }
@@ -1261,11 +1285,11 @@ void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *coun
             int lo = 0, hi = n_items - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (items[mid].first_wave <= wave) lo = mid; else hi = mid - 1;
+                if (as_constant(items)[mid].first_wave <= wave) lo = mid; else hi = mid - 1;
             }
             lo = uniform_i(lo);
-            const BatchItem &it = items[lo];
-            if (it.limit && wave - it.first_wave >= *it.limit) continue;
+            const BatchItem it = load_item(items, lo);
+            if (it.limit && wave - it.first_wave >= *as_constant(it.limit)) continue;
             const int idx = (int)(it.pt_offset + (wave - it.first_wave));
             track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
         }
