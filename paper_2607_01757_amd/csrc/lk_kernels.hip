@@ -1011,6 +1011,33 @@ struct PassResult {
     float res;         // mean |T - J| over the level-0 window
 };
 
+// The end of a pass at level 0: end point q = p + g + d (u = q - c in level
+// coordinates, fu = its floor as clamped for the tap base), the mean
+// |T - J(q + x)| over the window and the final in-frame check.
+template <class G>
+__device__ __forceinline__ void finish_level0(const LaneCfg &lc, int win, float nw, const float (&T)[G::R][G::CW],
+                                              const float (&jt)[G::R + 1][G::CW + 1], float ux, float uy, float fux,
+                                              float fuy, int cix, int ciy, float cfx, float cfy, const LevelDesc &LJ,
+                                              PassResult &pr)
+{
+    pr.ox = (float)cix + ux;
+    pr.oy = (float)ciy + uy;
+    pr.fx = ux - cfx;
+    pr.fy = uy - cfy;
+    const Weights w = bilinear_weights(ux - fux, uy - fuy);
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < G::R; ++i)
+#pragma unroll
+        for (int j = 0; j < G::CW; ++j) {
+            const float jv = bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
+            acc += c_valid(lc, win, i, j) ? fabsf(T[i][j] - jv) : 0.0f;
+        }
+    pr.res = uniform_f(wave_sum(acc)) / nw;
+    if (!(ux >= (float)(-cix) && ux <= (float)(LJ.w - 1 - cix) && uy >= (float)(-ciy) && uy <= (float)(LJ.h - 1 - ciy)))
+        pr.status = LK_LOST_OOB;
+}
+
 // One coarse-to-fine pass of pyramid I (template) into pyramid J (target).
 template <int ST, class G>
 __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, float py, float gx, float gy,
@@ -1154,38 +1181,35 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         if (l > 0) {
             gx = 2.0f * (gx + dx);
             gy = 2.0f * (gy + dy);
+            continue;
+        }
+        if constexpr (G::R <= 7 && ST == LK_STORAGE_F32) {
+            // level 0 of the 1x7 float32 kernel: the end point and the residual here,
+            // where the last iteration's taps serve unless the tap base moved
+            // (the other layouts and storages keep fewer registers live by
+            // reloading after the loop)
+            const float ux = (cfx + gx) + dx, uy = (cfy + gy) + dy;
+            const float fux = fminf(fmaxf(floorf(ux), (float)(-cix - h - 2)), (float)(LJ.w + h + 2 - cix));
+            const float fuy = fminf(fmaxf(floorf(uy), (float)(-ciy - h - 2)), (float)(LJ.h + h + 2 - ciy));
+            const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
+            if (bx != jbx || by != jby) {
+                const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
+                load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+            }
+            finish_level0<G>(lc, win, nw, T, jt, ux, uy, fux, fuy, cix, ciy, cfx, cfy, LJ, pr);
         }
     }
-    // level 0: c = p; end point q = p + g + d
-    const float ux = (cfx + gx) + dx, uy = (cfy + gy) + dy;
-    pr.ox = (float)cix + ux;
-    pr.oy = (float)ciy + uy;
-    pr.fx = ux - cfx;
-    pr.fy = uy - cfy;
-    {
+    if constexpr (!(G::R <= 7 && ST == LK_STORAGE_F32)) {
+        const float ux = (cfx + gx) + dx, uy = (cfy + gy) + dy;
         const LevelDesc LJ = uniform_level(J.lv[0]);
         const Plane PJ = make_plane<K_U8>(LJ.img, LJ.pitch, LJ.w, LJ.h);
-        // the last update is not range-checked: keep the tap base finite and
-        // near the frame before converting (taps are clamped anyway)
         const float fux = fminf(fmaxf(floorf(ux), (float)(-cix - h - 2)), (float)(LJ.w + h + 2 - cix));
         const float fuy = fminf(fmaxf(floorf(uy), (float)(-ciy - h - 2)), (float)(LJ.h + h + 2 - ciy));
         const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
         const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
         float jt[R + 1][CW + 1];
         load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
-        const Weights w = bilinear_weights(ux - fux, uy - fuy);
-        float acc = 0.0f;
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-#pragma unroll
-            for (int j = 0; j < CW; ++j) {
-                const float jv = bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
-                acc += c_valid(lc, win, i, j) ? fabsf(T[i][j] - jv) : 0.0f;
-            }
-        pr.res = uniform_f(wave_sum(acc)) / nw;
-        if (!(ux >= (float)(-cix) && ux <= (float)(LJ.w - 1 - cix) && uy >= (float)(-ciy)
-              && uy <= (float)(LJ.h - 1 - ciy)))
-            pr.status = LK_LOST_OOB;
+        finish_level0<G>(lc, win, nw, T, jt, ux, uy, fux, fuy, cix, ciy, cfx, cfy, LJ, pr);
     }
     return pr;
 }
