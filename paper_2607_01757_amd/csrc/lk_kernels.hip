@@ -268,14 +268,30 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
     const bool vec_ok = (j.spitch & 15) == 0 && (reinterpret_cast<uintptr_t>(j.src) & 15) == 0;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t *>(j.src), (short)0, j.spitch * j.sh, kBufWord3);
-    for (int i = threadIdx.x; i < kP0H * kP0Chunks; i += kThreads) {
+    //    every 16-byte load of a thread is issued before the first is
+    //    stored, so a thread waits for memory once, not once per chunk
+    constexpr int NCH = kP0H * kP0Chunks, PER = (NCH + kThreads - 1) / kThreads;
+    uint4 v[PER];
+    bool vec[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * kThreads;
         const int r = i / kP0Chunks, c = i - r * kP0Chunks;
         const int gy = reflect101(clampi(sy0 + r, -2, j.sh + 1), j.sh);
         const int x0 = a0 + 16 * c;
-        if (vec_ok && x0 >= 0 && x0 + 16 <= j.sw) {
-            *reinterpret_cast<uint4 *>(&sm.in[r][16 * c]) =
-                __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, gy * j.spitch + x0, 0, 0));
+        vec[q] = i < NCH && vec_ok && x0 >= 0 && x0 + 16 <= j.sw;
+        if (vec[q]) v[q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, gy * j.spitch + x0, 0, 0));
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        if (i >= NCH) continue;
+        const int r = i / kP0Chunks, c = i - r * kP0Chunks;
+        if (vec[q]) {
+            *reinterpret_cast<uint4 *>(&sm.in[r][16 * c]) = v[q];
         } else {
+            const int gy = reflect101(clampi(sy0 + r, -2, j.sh + 1), j.sh);
+            const int x0 = a0 + 16 * c;
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int gx = reflect101(clampi(x0 + k, -2, j.sw + 1), j.sw);
