@@ -453,7 +453,7 @@ struct alignas(16) SelSmem {
     uint32_t hist[SBLOCK / 64][256];           // one histogram per wavefront
     unsigned long long cmask[CHUNK][CHUNK / 64];   // conflicts with better candidates of the chunk
     unsigned long long sel[CHUNK / 64], und[CHUNK / 64];
-    uint32_t wcount;
+    uint32_t wcount, bcount;
     Key bound;
     int32_t done_flag;
     uint32_t need;
@@ -504,18 +504,24 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
         // ---- the next window: the best min(CAPW, remaining) candidates
         const int wn = remaining < CAPW ? remaining : CAPW;
         Key low{0, 0};                          // window = eligible keys >= low
+        // the list the passes read: the candidates, or, once few keys are at
+        // or above the boundary bucket, a copy of just those keys (in the
+        // frame's peak list, no longer needed after the compaction)
+        const GfttPeak *src = cand;
+        int nsrc = np;
+        bool filtered = false;
         if (wn < remaining) {
             uint32_t need = (uint32_t)wn;
             Key prefix{0, 0};
             for (int d = 0; d < 12; ++d) {
                 for (int k = tid; k < (SBLOCK / 64) * 256; k += SBLOCK) (&sm.hist[0][0])[k] = 0;
                 __syncthreads();
-                for (int k0 = 0; k0 < np; k0 += 8 * SBLOCK) {
+                for (int k0 = 0; k0 < nsrc; k0 += 8 * SBLOCK) {
                     Key key[8];
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int k = k0 + i * SBLOCK + tid;
-                        key[i] = k < np ? Key{cand[k].rbits, ~cand[k].idx} : Key{0, 0};
+                        key[i] = k < nsrc ? Key{src[k].rbits, ~src[k].idx} : Key{0, 0};
                     }
 #pragma unroll
                     for (int i = 0; i < 8; ++i)
@@ -548,6 +554,7 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                             sm.need = need - cum;
                             sm.done_flag = t[i] == need - cum ? 1 : 0;
                             sm.bound = key_set_byte(prefix, d, (uint32_t)(4 * lane + i));
+                            sm.bcount = t[i];
                         }
                         cum += t[i];
                     }
@@ -556,20 +563,44 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 need = sm.need;
                 prefix = sm.bound;
                 const bool whole = sm.done_flag != 0;
+                const int kept = (int)((uint32_t)wn - need + sm.bcount);   // keys >= the bucket's lower bound
                 __syncthreads();
                 if (whole) break;
+                if (!filtered && 4 * kept <= nsrc) {
+                    // copy the eligible keys >= prefix (its lower bytes are 0):
+                    // the keys above the bucket and the bucket itself
+                    if (tid == 0) sm.wcount = 0;
+                    __syncthreads();
+                    for (int k0 = 0; k0 < nsrc; k0 += SBLOCK) {
+                        const int k = k0 + tid;
+                        GfttPeak p{};
+                        bool take = false;
+                        if (k < nsrc) {
+                            p = src[k];
+                            const Key key{p.rbits, ~p.idx};
+                            take = eligible(key, bounded, bound) && !key_less(key, prefix);
+                        }
+                        const uint32_t at = wave_append(take, &sm.wcount);
+                        if (take) J.peaks[at] = p;
+                    }
+                    __syncthreads();             // the copy is visible to the whole workgroup
+                    src = J.peaks;
+                    nsrc = (int)sm.wcount;
+                    filtered = true;
+                    __syncthreads();
+                }
             }
             low = prefix;
         }
         // ---- gather the window and sort it (descending) in LDS
         if (tid == 0) sm.wcount = 0;
         __syncthreads();
-        for (int k0 = 0; k0 < np; k0 += 8 * SBLOCK) {
+        for (int k0 = 0; k0 < nsrc; k0 += 8 * SBLOCK) {
             Key key[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int k = k0 + i * SBLOCK + tid;
-                key[i] = k < np ? Key{cand[k].rbits, ~cand[k].idx} : Key{0, 0};
+                key[i] = k < nsrc ? Key{src[k].rbits, ~src[k].idx} : Key{0, 0};
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
