@@ -63,8 +63,10 @@ __device__ __forceinline__ float wave_sum(float v)
     v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
     v += dpp_move<0x141>(v);   // row_half_mirror: quad <-> quad within 8 lanes
     v += dpp_move<0x140>(v);   // row_mirror: half-row <-> half-row within 16 lanes
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+    // the row broadcasts write every row (a row without a source adds 0), so
+    // each is one DPP add; only lane 63's sum is read
+    v += dpp_move<0x142>(v);
+    v += dpp_move<0x143>(v);
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
@@ -703,6 +705,16 @@ __device__ __forceinline__ float bilerp(const Weights &w, float a, float b, floa
     return fmaf(w.w11, d, fmaf(w.w01, c, fmaf(w.w10, b, w.w00 * a)));
 }
 
+// The one-column layouts sample in lerp form instead: along each tap row
+// (left tap plus ax times the right-minus-left difference), then down the
+// column.  Template and target samples take the same operations on the same
+// taps, so equal frames still give an exactly zero mismatch; a row's
+// interpolation serves the two samples above and below it, and the target
+// taps are kept as (left, difference) pairs, so an iteration spends two
+// fused multiply-adds and one subtraction per sample.
+__device__ __forceinline__ float lerp_row(float ax, float left, float diff) { return fmaf(ax, diff, left); }
+__device__ __forceinline__ float lerp_col(float ay, float top, float bottom) { return fmaf(ay, bottom - top, top); }
+
 // Template data of level l in LDS.  E (SW x SH): the level region from
 // (tx_lo, ty_lo) with a one-pixel halo around the tap positions; GX, GY
 // (TW x TH): Scharr gradients at tap positions (tx_lo + 1 + tc, ty_lo + 1 +
@@ -798,7 +810,7 @@ __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty
 // position of tap plane entry (0, 0).
 template <class G>
 __device__ __forceinline__ void lane_template(const float *lds, const LaneCfg &lc, int win, const Weights &w,
-                                              int tx0, int ty0, int cx0, int cy0, int lw, int lh,
+                                              float ax, float ay, int tx0, int ty0, int cx0, int cy0, int lw, int lh,
                                               float (&T)[G::R][G::CW], float (&GX)[G::R][G::CW],
                                               float (&GY)[G::R][G::CW])
 {
@@ -819,7 +831,9 @@ __device__ __forceinline__ void lane_template(const float *lds, const LaneCfg &l
             const int t00 = cr[i] + cc[j], t10 = cr[i] + cc[j + 1], t01 = cr[i + 1] + cc[j], t11 = cr[i + 1] + cc[j + 1];
             const int e00 = er[i] + cc[j], e10 = er[i] + cc[j + 1], e01 = er[i + 1] + cc[j], e11 = er[i + 1] + cc[j + 1];
             const bool ok = c_valid(lc, win, i, j);
-            const float v = bilerp(w, E[e00], E[e10], E[e01], E[e11]);
+            const float v = G::CW == 1 ? lerp_col(ay, lerp_row(ax, E[e00], E[e10] - E[e00]),
+                                                  lerp_row(ax, E[e01], E[e11] - E[e01]))
+                                       : bilerp(w, E[e00], E[e10], E[e01], E[e11]);
             const float u = bilerp(w, TX[t00], TX[t10], TX[t01], TX[t11]);
             const float q = bilerp(w, TY[t00], TY[t10], TY[t01], TY[t11]);
             T[i][j] = ok ? v : 0.0f;
@@ -853,6 +867,18 @@ __device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, bool i
 #pragma unroll
         for (int j = 0; j <= G::CW; ++j) t[i][j] = bload<KIND>(P, row + xs[j]);
     }
+}
+
+// Target taps of a lane (load_taps); the one-column layouts keep each tap
+// row as (left, right - left) for lerp_row.
+template <class G, int KIND>
+__device__ __forceinline__ void load_lane_taps(const Plane &P, int bx, int by, bool inside,
+                                               float (&t)[G::R + 1][G::CW + 1])
+{
+    load_taps<G, KIND>(P, bx, by, inside, t);
+    if constexpr (G::CW == 1)
+#pragma unroll
+        for (int i = 0; i <= G::R; ++i) t[i][1] = t[i][1] - t[i][0];
 }
 
 // One element of a plane at byte offset voff + soff (soff: a wave-uniform
@@ -951,7 +977,7 @@ __device__ __forceinline__ void load_rect(const Plane &P, int x0, int y0, bool i
 // the level bilinearly (both are linear filters with the same weights at
 // every window position); only the rounding order differs.
 template <class G, int KIND>
-__device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_lo, const Weights &w,
+__device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_lo, float ax, float ay,
                                               const LaneCfg &lc, int win, int lane, float *lds,
                                               float (&T)[G::R][G::CW], float (&GX)[G::R][G::CW],
                                               float (&GY)[G::R][G::CW])
@@ -962,29 +988,28 @@ __device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_
     load_rect<KIND, SW, SH>(P, tx_lo, ty_lo, true, lane, E);
     wave_lds_sync();
     {
-        // lanes beyond the groups, and rows past the grid, repeat an entry
-        // another lane writes (same value), so nothing is predicated
-        constexpr int NG = 64 / TBW, KS = (TBH + NG - 1) / NG;
-        constexpr bool RAGGED = KS * NG != TBH;
+        // lanes are Tb columns, NG groups of RPG consecutive rows side by side
+        // (the last group starts RPG rows before the end, so an overlapped row
+        // is computed twice from the same data and written with the same
+        // bits); lanes beyond the groups repeat a lane of their half
+        constexpr int NG = 64 / TBW, RPG = (TBH + NG - 1) / NG;
         int g, b;
         group_lane<TBW, NG>(lane, g, b);
-        constexpr int KB = KS <= 12 ? KS : 8;
+        const int g0 = min(g * RPG, TBH - RPG);
+        const float *e = E + g0 * SW + b;
+        float *t = Tb + g0 * TBS + b;
+        float h0 = lerp_row(ax, e[0], e[1] - e[0]);
+        constexpr int KB = RPG <= 12 ? RPG : 8;
 #pragma unroll 1
-        for (int k0 = 0; k0 < KS; k0 += KB) {
-            const float *e = E + (g + NG * k0) * SW + b;
-            float *t = Tb + (g + NG * k0) * TBS + b;
+        for (int k0 = 0; k0 < RPG; k0 += KB) {
 #pragma unroll
             for (int kk = 0; kk < KB; ++kk) {
                 const int k = k0 + kk;
-                if (k >= KS) break;
-                if (RAGGED && k == KS - 1) {
-                    const int a2 = min(g + NG * k, TBH - 1);
-                    const float *q = E + a2 * SW + b;
-                    Tb[a2 * TBS + b] = bilerp(w, q[0], q[1], q[SW], q[SW + 1]);
-                } else {
-                    const float *q = e + kk * NG * SW;
-                    t[kk * NG * TBS] = bilerp(w, q[0], q[1], q[SW], q[SW + 1]);
-                }
+                if (k >= RPG) break;
+                const float *q = e + (k + 1) * SW;
+                const float h1 = lerp_row(ax, q[0], q[1] - q[0]);
+                t[k * TBS] = lerp_col(ay, h0, h1);
+                h0 = h1;
             }
         }
     }
@@ -1040,15 +1065,26 @@ __device__ __forceinline__ void finish_level0(const LaneCfg &lc, int win, float 
     pr.oy = (float)ciy + uy;
     pr.fx = ux - cfx;
     pr.fy = uy - cfy;
-    const Weights w = bilinear_weights(ux - fux, uy - fuy);
     float acc = 0.0f;
+    if constexpr (G::CW == 1) {
+        const float ax = ux - fux, ay = uy - fuy;
+        float h0 = lerp_row(ax, jt[0][0], jt[0][1]);
 #pragma unroll
-    for (int i = 0; i < G::R; ++i)
-#pragma unroll
-        for (int j = 0; j < G::CW; ++j) {
-            const float jv = bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
-            acc += c_valid(lc, win, i, j) ? fabsf(T[i][j] - jv) : 0.0f;
+        for (int i = 0; i < G::R; ++i) {
+            const float h1 = lerp_row(ax, jt[i + 1][0], jt[i + 1][1]);
+            acc += c_valid(lc, win, i, 0) ? fabsf(T[i][0] - lerp_col(ay, h0, h1)) : 0.0f;
+            h0 = h1;
         }
+    } else {
+        const Weights w = bilinear_weights(ux - fux, uy - fuy);
+#pragma unroll
+        for (int i = 0; i < G::R; ++i)
+#pragma unroll
+            for (int j = 0; j < G::CW; ++j) {
+                const float jv = bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
+                acc += c_valid(lc, win, i, j) ? fabsf(T[i][j] - jv) : 0.0f;
+            }
+    }
     pr.res = uniform_f(wave_sum(acc)) / nw;
     if (!(ux >= (float)(-cix) && ux <= (float)(LJ.w - 1 - cix) && uy >= (float)(-ciy) && uy <= (float)(LJ.h - 1 - ciy)))
         pr.status = LK_LOST_OOB;
@@ -1091,19 +1127,18 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
                 fast = tx_lo >= 0 && ty_lo >= 0 && tx_lo + G::SW <= LI.w && ty_lo + G::SH <= LI.h;
             if (fast) {
                 if constexpr (ST == LK_STORAGE_F32 && G::CW == 1) {
-                    const Weights wt = bilinear_weights(cfx, cfy);
                     if (l == 0)
-                        fast_template<G, K_U8>(make_plane<K_U8>(LI.img, LI.pitch, LI.w, LI.h), tx_lo, ty_lo, wt, lc,
-                                               win, lane, lds, T, GX, GY);
+                        fast_template<G, K_U8>(make_plane<K_U8>(LI.img, LI.pitch, LI.w, LI.h), tx_lo, ty_lo, cfx, cfy,
+                                               lc, win, lane, lds, T, GX, GY);
                     else
-                        fast_template<G, K_F32>(make_plane<K_F32>(LI.img, LI.pitch, LI.w, LI.h), tx_lo, ty_lo, wt,
-                                                lc, win, lane, lds, T, GX, GY);
+                        fast_template<G, K_F32>(make_plane<K_F32>(LI.img, LI.pitch, LI.w, LI.h), tx_lo, ty_lo, cfx,
+                                                cfy, lc, win, lane, lds, T, GX, GY);
                 }
             } else {
                 if (l == 0) stage_taps<G, K_U8, ST == LK_STORAGE_F16>(LI, tx_lo, ty_lo, lane, lds);
                 else if constexpr (ST == LK_STORAGE_F16) stage_taps<G, K_F16, true>(LI, tx_lo, ty_lo, lane, lds);
                 else stage_taps<G, K_F32, false>(LI, tx_lo, ty_lo, lane, lds);
-                lane_template<G>(lds, lc, win, bilinear_weights(cfx, cfy), cix - h + lc.c0, ciy - h + lc.r0,
+                lane_template<G>(lds, lc, win, bilinear_weights(cfx, cfy), cfx, cfy, cix - h + lc.c0, ciy - h + lc.r0,
                                  cix - h, ciy - h, LI.w, LI.h, T, GX, GY);
             }
         }
@@ -1162,22 +1197,35 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
             if (bx != jbx || by != jby) {
                 const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
-                if (l == 0) load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                if (l == 0) load_lane_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
                 else if constexpr (ST == LK_STORAGE_F16)
-                    load_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
-                else load_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                    load_lane_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                else load_lane_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
                 jbx = bx; jby = by;
             }
-            const Weights w = bilinear_weights(ux - fux, uy - fuy);
             float bxs = 0.0f, bys = 0.0f;
+            if constexpr (CW == 1) {
+                const float ax = ux - fux, ay = uy - fuy;
+                float h0 = lerp_row(ax, jt[0][0], jt[0][1]);
 #pragma unroll
-            for (int i = 0; i < R; ++i)
-#pragma unroll
-                for (int j = 0; j < CW; ++j) {
-                    const float e = T[i][j] - bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
-                    bxs = fmaf(e, GX[i][j], bxs);
-                    bys = fmaf(e, GY[i][j], bys);
+                for (int i = 0; i < R; ++i) {
+                    const float h1 = lerp_row(ax, jt[i + 1][0], jt[i + 1][1]);
+                    const float e = T[i][0] - lerp_col(ay, h0, h1);
+                    bxs = fmaf(e, GX[i][0], bxs);
+                    bys = fmaf(e, GY[i][0], bys);
+                    h0 = h1;
                 }
+            } else {
+                const Weights w = bilinear_weights(ux - fux, uy - fuy);
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+#pragma unroll
+                    for (int j = 0; j < CW; ++j) {
+                        const float e = T[i][j] - bilerp(w, jt[i][j], jt[i][j + 1], jt[i + 1][j], jt[i + 1][j + 1]);
+                        bxs = fmaf(e, GX[i][j], bxs);
+                        bys = fmaf(e, GY[i][j], bys);
+                    }
+            }
             const float bx_ = uniform_f(wave_sum(bxs)), by_ = uniform_f(wave_sum(bys));
             const float ex = (Gyy * bx_ - Gxy * by_) * rdet;
             const float ey = (Gxx * by_ - Gxy * bx_) * rdet;
@@ -1210,7 +1258,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
             if (bx != jbx || by != jby) {
                 const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
-                load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                load_lane_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
             }
             finish_level0<G>(lc, win, nw, T, jt, ux, uy, fux, fuy, cix, ciy, cfx, cfy, LJ, pr);
         }
@@ -1224,7 +1272,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
         const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
         float jt[R + 1][CW + 1];
-        load_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+        load_lane_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
         finish_level0<G>(lc, win, nw, T, jt, ux, uy, fux, fuy, cix, ciy, cfx, cfy, LJ, pr);
     }
     return pr;
@@ -1245,10 +1293,22 @@ __device__ void track_point(const PyrDesc &prev, const PyrDesc &next, const Trac
     int32_t *itp = a.iters ? a.iters + (size_t)idx * 2 * L : nullptr;
     if (itp && lc.lane0)
         for (int l = 0; l < 2 * L; ++l) itp[l] = 0;
-    PassResult f = run_pass<ST, G>(prev, next, px, py, gx, gy, a, lc, lane, lds, itp);
+    // the one-column layouts inline both passes (their LDS accesses stay
+    // local-data-share instructions); the wide layout is left to the compiler
+    PassResult f, b;
+    if constexpr (G::CW == 1) {
+        [[clang::always_inline]] f = run_pass<ST, G>(prev, next, px, py, gx, gy, a, lc, lane, lds, itp);
+    } else {
+        f = run_pass<ST, G>(prev, next, px, py, gx, gy, a, lc, lane, lds, itp);
+    }
     int status = f.status;
     if (status == LK_OK && a.fb_thresh > 0.0f) {
-        PassResult b = run_pass<ST, G>(next, prev, f.ox, f.oy, 0.0f, 0.0f, a, lc, lane, lds, itp ? itp + L : nullptr);
+        int32_t *itb = itp ? itp + L : nullptr;
+        if constexpr (G::CW == 1) {
+            [[clang::always_inline]] b = run_pass<ST, G>(next, prev, f.ox, f.oy, 0.0f, 0.0f, a, lc, lane, lds, itb);
+        } else {
+            b = run_pass<ST, G>(next, prev, f.ox, f.oy, 0.0f, 0.0f, a, lc, lane, lds, itb);
+        }
         if (b.status != LK_OK) {
             status = LK_LOST_FB;
         } else {
@@ -1277,7 +1337,11 @@ void k_track(const PyrDesc *prev, const PyrDesc *next, TrackArgs a)
     const int wib = threadIdx.x >> 6;
     const int wave = uniform_i(xcd_block(blockIdx.x, gridDim.x) * G::WPB + wib);
     if (wave >= a.n) return;
-    track_point<ST, G>(*prev, *next, a, wave, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
+    if constexpr (G::CW == 1) {
+        [[clang::always_inline]] track_point<ST, G>(*prev, *next, a, wave, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
+    } else {
+        track_point<ST, G>(*prev, *next, a, wave, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
+    }
 }
 
 template <int ST, class G>
@@ -1297,7 +1361,11 @@ void k_track_batched(const BatchItem *items, int n_items, TrackArgs a)
     const BatchItem it = load_item(items, lo);
     if (it.limit && wave - it.first_wave >= *as_constant(it.limit)) return;   // past the item's live count
     const int idx = (int)(it.pt_offset + (wave - it.first_wave));
-    track_point<ST, G>(*it.prev, *it.next, a, idx, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
+    if constexpr (G::CW == 1) {
+        [[clang::always_inline]] track_point<ST, G>(*it.prev, *it.next, a, idx, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
+    } else {
+        track_point<ST, G>(*it.prev, *it.next, a, idx, threadIdx.x & (kWave - 1), s_lds + wib * G::LDS);
+    }
 }
 
 // Persistent form: a fixed grid whose wavefronts take keypoints from work
@@ -1331,7 +1399,11 @@ void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *coun
             const BatchItem it = load_item(items, lo);
             if (it.limit && wave - it.first_wave >= *as_constant(it.limit)) continue;
             const int idx = (int)(it.pt_offset + (wave - it.first_wave));
-            track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
+            if constexpr (G::CW == 1) {
+                [[clang::always_inline]] track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
+            } else {
+                track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
+            }
         }
     }
 }
