@@ -635,20 +635,17 @@ struct Geo {
     // column walk of the gradient build: lanes are tap columns, GROUPS row
     // groups side by side, RPG tap rows each
     static constexpr int TBW = EXX + 2, TBH = EXY + 2;         // interpolated template incl. a one-pixel halo
-    // LDS row strides of the tap region and of the interpolated template,
-    // chosen so that the lane segments of a wavefront (rows r0 = 0, R, 2R)
-    // fall on disjoint banks: the LDS serves a wavefront as two halves of 32
-    // lanes over 32 banks, and 7 x 67 = 21, 14 x 67 = 10 (mod 32) put the
-    // 21-lane segments of the 1x7 layout on banks 0-20 and 21-31 (first half),
-    // 0-9 and 10-30 (second half); 16 x 34 = 0 (mod 32) with 31-lane segments
-    // gives one segment per half for the 1x16 layout
-    static constexpr int RS = CW == 1 && R == 7 ? 67 : (CW == 1 && R == 16 ? 34 : (TW | 1));
-    static constexpr int TBS = RS > TBW ? RS : (TBW | 1);
+    // LDS row stride of the interpolated template, chosen so that the lane
+    // segments of a wavefront (rows r0 = 0, R, 2R) fall on disjoint banks:
+    // the LDS serves a wavefront as two halves of 32 lanes over 32 banks,
+    // and 7 x 35 = 21, 14 x 35 = 10 (mod 32) put the 21-lane segments of the
+    // 1x7 layout on banks 0-20 and 21-31 (first half), 0-9 and 10-30 (second
+    // half); 16 x 34 = 0 (mod 32) with 31-lane segments gives one segment per
+    // half for the 1x16 layout
+    static constexpr int TBS = CW == 1 && R == 7 ? 35 : (CW == 1 && R == 16 ? 34 : (TBW | 1));
     static constexpr int LDS_OLD = SW * SH + 2 * TW * TH;      // staged level + two gradient planes
     static constexpr int LDS_FAST = SW * SH + TBS * TBH;       // staged level + interpolated template
-    static constexpr int LDS_REG = RS * TH;                    // target tap region
-    static constexpr int LDS = LDS_OLD > LDS_FAST ? (LDS_OLD > LDS_REG ? LDS_OLD : LDS_REG)
-                                                  : (LDS_FAST > LDS_REG ? LDS_FAST : LDS_REG);   // floats per wave
+    static constexpr int LDS = LDS_OLD > LDS_FAST ? LDS_OLD : LDS_FAST;   // floats per wave
     static constexpr int CPASS = (TW + 63) / 64;
     static constexpr int GROUPS = TW <= 64 ? 64 / TW : 1;
     static constexpr int RPG = (TH + GROUPS - 1) / GROUPS;
@@ -732,6 +729,12 @@ __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty
 {
     float *E = lds, *TX = lds + G::SW * G::SH, *TY = TX + G::TW * G::TH;
     const Plane P = make_plane<KIND>(L.img, L.pitch, L.w, L.h);
+    // this path serves windows near a level edge only: an opaque copy of the
+    // lane index keeps its per-lane index arithmetic here instead of letting
+    // the compiler hoist it into every pass (registers and instructions the
+    // common path would pay for)
+    asm volatile("" : "+v"(lane));
+    lane &= kWave - 1;
     if constexpr (!PLANES) {
         // region inside the level (the common case): no reflection needed
         const bool inside = tx_lo >= 0 && ty_lo >= 0 && tx_lo + G::SW <= L.w && ty_lo + G::SH <= L.h;
@@ -1031,18 +1034,6 @@ __device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_
         }
         d0 = d1; d1 = d2; s0 = s1; s1 = s2; c1 = c;
     }
-}
-
-// Taps of this lane from a target region loaded by load_rect at the lane's
-// window origin (region row stride G::RS).
-template <class G>
-__device__ __forceinline__ void region_taps(const float *region, const LaneCfg &lc, float (&t)[G::R + 1][G::CW + 1])
-{
-    const float *q = region + lc.r0 * G::RS + lc.c0;
-#pragma unroll
-    for (int i = 0; i <= G::R; ++i)
-#pragma unroll
-        for (int j = 0; j <= G::CW; ++j) t[i][j] = q[i * G::RS + j];
 }
 
 struct PassResult {
