@@ -608,6 +608,17 @@ __device__ __forceinline__ float bload(const Plane &p, int idx)
     else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs, idx * 4, 0, 0));
 }
 
+// One element of a plane at byte offset voff + soff (soff: a wave-uniform
+// offset that the load takes from a scalar register).
+template <int KIND>
+__device__ __forceinline__ float bload_at(const Plane &p, int voff, int soff)
+{
+    if constexpr (KIND == K_U8) return (float)__builtin_amdgcn_raw_buffer_load_b8(p.rs, voff, soff, 0);
+    else if constexpr (KIND == K_F16)
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(p.rs, voff, soff, 0)));
+    else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs, voff, soff, 0));
+}
+
 __device__ __forceinline__ float2 bload_h2(const __amdgpu_buffer_rsrc_t &rs, int idx)
 {
     return __half22float2(__builtin_bit_cast(__half2, __builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4, 0, 0)));
@@ -854,11 +865,24 @@ __device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, bool i
                                           float (&t)[G::R + 1][G::CW + 1])
 {
     if (inside) {
-        const int base = by * P.pitch + bx;
+        if constexpr (G::R <= 7) {
+            // one vector offset for the lane's first tap; the row offsets are
+            // wave-uniform and go in the scalar offset of each load (taller
+            // strips keep per-row vector offsets: their scalar registers are
+            // short)
+            constexpr int es = KIND == K_U8 ? 1 : (KIND == K_F16 ? 2 : 4);
+            const int voff = (by * P.pitch + bx) * es;
 #pragma unroll
-        for (int i = 0; i <= G::R; ++i)
+            for (int i = 0; i <= G::R; ++i)
 #pragma unroll
-            for (int j = 0; j <= G::CW; ++j) t[i][j] = bload<KIND>(P, base + i * P.pitch + j);
+                for (int j = 0; j <= G::CW; ++j) t[i][j] = bload_at<KIND>(P, voff + j * es, i * P.pitch * es);
+        } else {
+            const int base = by * P.pitch + bx;
+#pragma unroll
+            for (int i = 0; i <= G::R; ++i)
+#pragma unroll
+                for (int j = 0; j <= G::CW; ++j) t[i][j] = bload<KIND>(P, base + i * P.pitch + j);
+        }
         return;
     }
     int xs[G::CW + 1];
@@ -882,17 +906,6 @@ __device__ __forceinline__ void load_lane_taps(const Plane &P, int bx, int by, b
     if constexpr (G::CW == 1)
 #pragma unroll
         for (int i = 0; i <= G::R; ++i) t[i][1] = t[i][1] - t[i][0];
-}
-
-// One element of a plane at byte offset voff + soff (soff: a wave-uniform
-// offset that the load takes from a scalar register).
-template <int KIND>
-__device__ __forceinline__ float bload_at(const Plane &p, int voff, int soff)
-{
-    if constexpr (KIND == K_U8) return (float)__builtin_amdgcn_raw_buffer_load_b8(p.rs, voff, soff, 0);
-    else if constexpr (KIND == K_F16)
-        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(p.rs, voff, soff, 0)));
-    else return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(p.rs, voff, soff, 0));
 }
 
 // Row group g and column c of a lane when NG groups of RW lanes lie side by
@@ -1170,10 +1183,25 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         const Plane PJ = l == 0 ? make_plane<K_U8>(LJ.img, LJ.pitch, LJ.w, LJ.h)
                                 : (ST == LK_STORAGE_F16 ? make_plane<K_F16>(LJ.img, LJ.pitch, LJ.w, LJ.h)
                                                         : make_plane<K_F32>(LJ.img, LJ.pitch, LJ.w, LJ.h));
-        // target taps of this level: loaded at the first iteration and
-        // whenever the integer part of the estimate moves
+        // target taps of this level, whose first tap sits at (bx - h, by - h)
         float jt[R + 1][CW + 1];
-        int jbx = INT_MIN, jby = INT_MIN;
+        auto load_target = [&](int bx, int by) {
+            const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
+            if (l == 0) load_lane_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+            else if constexpr (ST == LK_STORAGE_F16)
+                load_lane_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+            else load_lane_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+        };
+        // The taps of the first estimate are loaded before the iterations
+        // (its integer part clamped to the level's range: an estimate outside
+        // ends the pass before any tap is read, and the clamped loads stay in
+        // the level), then again whenever the integer part moves.  Loading
+        // here, rather than at the first iteration, also keeps the previous
+        // level's taps from flowing into this level (which costs a register
+        // copy of every tap per level).
+        int jbx = uniform_i(cix + (int)fminf(fmaxf(floorf(cfx + gx), lox), hix));
+        int jby = uniform_i(ciy + (int)fminf(fmaxf(floorf(cfy + gy), loy), hiy));
+        load_target(jbx, jby);
         dx = 0.0f; dy = 0.0f;
         int k = 0;
         bool oob = false;
@@ -1187,11 +1215,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             const float fux = floorf(ux), fuy = floorf(uy);
             const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
             if (bx != jbx || by != jby) {
-                const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
-                if (l == 0) load_lane_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
-                else if constexpr (ST == LK_STORAGE_F16)
-                    load_lane_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
-                else load_lane_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                load_target(bx, by);
                 jbx = bx; jby = by;
             }
             float bxs = 0.0f, bys = 0.0f;
@@ -1247,10 +1271,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             const float fux = fminf(fmaxf(floorf(ux), (float)(-cix - h - 2)), (float)(LJ.w + h + 2 - cix));
             const float fuy = fminf(fmaxf(floorf(uy), (float)(-ciy - h - 2)), (float)(LJ.h + h + 2 - ciy));
             const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
-            if (bx != jbx || by != jby) {
-                const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
-                load_lane_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
-            }
+            if (bx != jbx || by != jby) load_target(bx, by);
             finish_level0<G>(lc, win, nw, T, jt, ux, uy, fux, fuy, cix, ciy, cfx, cfy, LJ, pr);
         }
     }
