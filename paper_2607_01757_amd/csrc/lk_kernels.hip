@@ -259,12 +259,13 @@ __device__ __forceinline__ float to_storage(float v, bool f16)
     return f16 ? __half2float(__float2half_rn(v)) : v;
 }
 
+template <bool F16>
 __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
 {
     const int ox2 = (tile % j.tiles_x) * kP12TileW, oy2 = (tile / j.tiles_x) * kP12TileH;
     const int rx1 = 2 * ox2 - 2, ry1 = 2 * oy2 - 2;          // level-1 region origin
     const int a0 = 4 * ox2 - 16, sy0 = 2 * ry1 - 2;          // level-0 staging origin (16-byte aligned x)
-    const bool f16 = j.f16 != 0;
+    constexpr bool f16 = F16;
     // 1. level 0 rows [sy0, sy0 + 73) x columns [a0, a0 + 160) as bytes;
     //    samples outside the frame hold the reflect-101 sample
     const bool vec_ok = (j.spitch & 15) == 0 && (reinterpret_cast<uintptr_t>(j.src) & 15) == 0;
@@ -317,26 +318,33 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
             // taps of columns c and c + 1 are staged bytes 2c+10 .. 2c+16, inside
             // the dwords at bytes [2c+8, 2c+20) (4-byte aligned: c is even)
             const uint32_t *col = reinterpret_cast<const uint32_t *>(&sm.in[0][2 * c + 8]);
-            auto byte_f = [](uint32_t w, int k) { return (float)((w >> (8 * k)) & 0xFFu); };
-            auto hsum2 = [&](int row, float &a, float &b) {
+            // On 8-bit data the binomial filter is exact in float (see
+            // binom5), so it is formed here in integers: the horizontal sums
+            // (weights 1 4 6 4 1, at most 255 x 16) and the vertical sum of
+            // five of them (at most 255 x 256), then one conversion and the
+            // scaling by 1 / 256, both exact: the same bits as binom5 twice.
+            auto hsum2 = [&](int row, uint32_t &a, uint32_t &b) {
                 const uint32_t *q = col + row * (kP0W / 4);
                 const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
-                const float t2 = byte_f(w0, 2), t3 = byte_f(w0, 3), t4 = byte_f(w1, 0), t5 = byte_f(w1, 1);
-                const float t6 = byte_f(w1, 2), t7 = byte_f(w1, 3), t8 = byte_f(w2, 0);
-                a = binom5(t2, t3, t4, t5, t6);
-                b = binom5(t4, t5, t6, t7, t8);
+                const uint32_t t2 = (w0 >> 16) & 0xFFu, t3 = w0 >> 24, t4 = w1 & 0xFFu, t5 = (w1 >> 8) & 0xFFu;
+                const uint32_t t6 = (w1 >> 16) & 0xFFu, t7 = w1 >> 24, t8 = w2 & 0xFFu;
+                a = (t2 + t6) + 4u * (t3 + t5) + 6u * t4;
+                b = (t4 + t8) + 4u * (t5 + t7) + 6u * t6;
+            };
+            auto vsum = [](uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3, uint32_t s4) {
+                return (float)((s0 + s4) + 4u * (s1 + s3) + 6u * s2) * (1.0f / 256.0f);
             };
             // output row r uses level-0 staged rows 2 r .. 2 r + 4
-            float a0, b0, a1, b1, a2, b2;
+            uint32_t a0, b0, a1, b1, a2, b2;
             hsum2(2 * r_lo, a0, b0);
             hsum2(2 * r_lo + 1, a1, b1);
             hsum2(2 * r_lo + 2, a2, b2);
             for (int r = r_lo; r < r_hi; ++r) {
-                float a3, b3, a4, b4;
+                uint32_t a3, b3, a4, b4;
                 hsum2(2 * r + 3, a3, b3);
                 hsum2(2 * r + 4, a4, b4);
-                sm.l1[r][c] = to_storage(binom5(a0, a1, a2, a3, a4), f16);
-                sm.l1[r][c + 1] = to_storage(binom5(b0, b1, b2, b3, b4), f16);
+                sm.l1[r][c] = to_storage(vsum(a0, a1, a2, a3, a4), f16);
+                sm.l1[r][c + 1] = to_storage(vsum(b0, b1, b2, b3, b4), f16);
                 a0 = a2; a1 = a3; a2 = a4;
                 b0 = b2; b1 = b3; b2 = b4;
             }
@@ -353,7 +361,7 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
 #pragma unroll
             for (int k = 0; k < 8; ++k) v[k] = sm.l1[r + 2][c + 2 + k];
             if (x1 + 7 < j.w1) {
-                if (f16) {
+                if constexpr (f16) {
                     uint4 u;
                     u.x = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[0], v[1]));
                     u.y = __builtin_bit_cast(uint32_t, __floats2half2_rn(v[2], v[3]));
@@ -369,7 +377,7 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
                     if (x1 + k < j.w1) {
-                        if (f16) static_cast<__half *>(j.dst1)[(size_t)y1 * j.pitch1 + x1 + k] = __float2half_rn(v[k]);
+                        if constexpr (f16) static_cast<__half *>(j.dst1)[(size_t)y1 * j.pitch1 + x1 + k] = __float2half_rn(v[k]);
                         else static_cast<float *>(j.dst1)[(size_t)y1 * j.pitch1 + x1 + k] = v[k];
                     }
             }
@@ -383,10 +391,12 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
         float v = 0.0f;
         if (ox2 + c < j.w2) {           // columns past level 2 are never used
             float q[5];
+            if (x_inside) {
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const int x1 = rx1 + 2 * c + k;
-                q[k] = sm.l1[r][(x_inside ? x1 : reflect101(x1, j.w1)) - rx1];
+                for (int k = 0; k < 5; ++k) q[k] = sm.l1[r][2 * c + k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) q[k] = sm.l1[r][reflect101(rx1 + 2 * c + k, j.w1) - rx1];
             }
             v = binom5(q[0], q[1], q[2], q[3], q[4]);
         }
@@ -399,18 +409,23 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
         const int r = threadIdx.x >> 4, c = (threadIdx.x & 15) * 2;
         const int y2 = oy2 + r, x2 = ox2 + c;
         if (y2 < j.h2) {
+            // region row of level-1 row 2 y2 - 2 + k: 2 r + k when the region
+            // lies inside level 1, else that row reflected into level 1
+            const bool y_inside = ry1 >= 0 && ry1 + kP1H <= j.h1;
             float v[2];
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
                 float q[5];
+                if (y_inside) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    const int y1 = 2 * y2 - 2 + k;
-                    q[k] = sm.h2[reflect101(y1, j.h1) - ry1][c + m];
+                    for (int k = 0; k < 5; ++k) q[k] = sm.h2[2 * r + k][c + m];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) q[k] = sm.h2[reflect101(2 * y2 - 2 + k, j.h1) - ry1][c + m];
                 }
                 v[m] = binom5(q[0], q[1], q[2], q[3], q[4]);
             }
-            if (f16) {
+            if constexpr (f16) {
                 __half *d = static_cast<__half *>(j.dst2) + (size_t)y2 * j.pitch2 + x2;
                 if (x2 + 1 < j.w2) *reinterpret_cast<__half2 *>(d) = __floats2half2_rn(v[0], v[1]);
                 else if (x2 < j.w2) d[0] = __float2half_rn(v[0]);
@@ -426,7 +441,9 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
 __global__ __launch_bounds__(kThreads) void k_pyr12(Pyr12Job j)
 {
     __shared__ P12Smem sm;
-    pyr12_tile(j, xcd_block(blockIdx.x, gridDim.x), sm);
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    if (j.f16) pyr12_tile<true>(j, tile, sm);
+    else pyr12_tile<false>(j, tile, sm);
 }
 
 __global__ __launch_bounds__(kThreads) void k_pyr12_batched(const Pyr12Job *jobs, const int32_t *tile_job)
@@ -434,7 +451,8 @@ __global__ __launch_bounds__(kThreads) void k_pyr12_batched(const Pyr12Job *jobs
     __shared__ P12Smem sm;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const Pyr12Job j = jobs[uniform_i(tile_job[tile])];
-    pyr12_tile(j, tile - j.tile_begin, sm);
+    if (j.f16) pyr12_tile<true>(j, tile - j.tile_begin, sm);
+    else pyr12_tile<false>(j, tile - j.tile_begin, sm);
 }
 
 // ------------------------------------------------------ binary16 gradient planes
