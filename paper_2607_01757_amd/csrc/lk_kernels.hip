@@ -21,6 +21,7 @@
 #include "lk_internal.h"
 
 #include <climits>
+#include <type_traits>
 
 namespace lkmi {
 namespace {
@@ -249,9 +250,11 @@ constexpr int kP0Chunks = 10;                                           // 16-by
 constexpr int kP0W = 16 * kP0Chunks;                                    // staged level-0 columns 160
 
 struct alignas(16) P12Smem {
-    uint8_t in[kP0H][kP0W];
+    union {                                   // the staged bytes are dead once level 1 is formed
+        uint8_t in[kP0H][kP0W];
+        float h2[kP1H][kP12TileW + 1];
+    };
     float l1[kP1H][kP1W + 1];
-    float h2[kP1H][kP12TileW + 1];
 };
 
 __device__ __forceinline__ float to_storage(float v, bool f16)
@@ -653,9 +656,12 @@ __device__ __forceinline__ void wave_lds_sync()
 // Lane layout of the window: lane (cg, sg) owns CW columns x R rows of
 // window pixels starting at (c0, r0).  WMAX is the largest window of the
 // layout; it fixes the staged regions.
-template <int CW_, int R_, int WMAX_, int WPB_, int OCC_>
+template <int CW_, int R_, int WMAX_, int WPB_, int OCC_, bool EXACT_ = false>
 struct Geo {
     static constexpr int CW = CW_, R = R_, WMAX = WMAX_, WPB = WPB_;
+    // EXACT: a build for win = WMAX only, where the strips tile the window
+    // exactly (every row of an active lane is valid)
+    static constexpr bool EXACT = EXACT_;
     static constexpr int OCC = OCC_;                           // wavefronts per SIMD the registers must allow
     static constexpr int EXX = ((WMAX + CW - 1) / CW) * CW;   // window columns covered by lanes
     static constexpr int EXY = ((WMAX + R - 1) / R) * R;
@@ -672,6 +678,13 @@ struct Geo {
     // half); 16 x 34 = 0 (mod 32) with 31-lane segments gives one segment per
     // half for the 1x16 layout
     static constexpr int TBS = CW == 1 && R == 7 ? 35 : (CW == 1 && R == 16 ? 34 : (TBW | 1));
+    // first of four zero columns past the template in rows 0 .. R+1 (1x7
+    // layout): with the lane segments above, the active lanes of the second
+    // half leave bank 31 + 3 a free at row a, so an idle lane reading there
+    // adds no conflict; -1: not used
+    static constexpr int ZC = CW == 1 && R == 7 ? 31 : -1;
+    static_assert(ZC < 0 || (ZC >= TBW && ZC + 4 <= TBS), "zero block inside the template rows");
+    static_assert(!EXACT || (EXX == WMAX && EXY == WMAX && ZC >= 0), "exact build of a layout that tiles the window");
     static constexpr int LDS_OLD = SW * SH + 2 * TW * TH;      // staged level + two gradient planes
     static constexpr int LDS_FAST = SW * SH + TBS * TBH;       // staged level + interpolated template
     static constexpr int LDS = LDS_OLD > LDS_FAST ? LDS_OLD : LDS_FAST;   // floats per wave
@@ -691,6 +704,7 @@ struct LaneCfg {
 template <class G>
 __device__ __forceinline__ LaneCfg lane_cfg(int win, int lane)
 {
+    if constexpr (G::EXACT) win = G::WMAX;
     const int ncg = (win + G::CW - 1) / G::CW, nsg = (win + G::R - 1) / G::R;
     LaneCfg c;
     c.active = lane < ncg * nsg;
@@ -707,6 +721,15 @@ __device__ __forceinline__ LaneCfg lane_cfg(int win, int lane)
 __device__ __forceinline__ bool c_valid(const LaneCfg &c, int win, int i, int j)
 {
     return c.active && (c.r0 + i < win) && (c.c0 + j < win);
+}
+
+// c_valid for layout G (in an exact build every pixel of an active lane is
+// in the window)
+template <class G>
+__device__ __forceinline__ bool g_valid(const LaneCfg &c, int win, int i, int j)
+{
+    if constexpr (G::EXACT) return c.active;
+    else return c_valid(c, win, i, j);
 }
 
 struct Weights {
@@ -862,7 +885,7 @@ __device__ __forceinline__ void lane_template(const float *lds, const LaneCfg &l
         for (int j = 0; j < G::CW; ++j) {
             const int t00 = cr[i] + cc[j], t10 = cr[i] + cc[j + 1], t01 = cr[i + 1] + cc[j], t11 = cr[i + 1] + cc[j + 1];
             const int e00 = er[i] + cc[j], e10 = er[i] + cc[j + 1], e01 = er[i + 1] + cc[j], e11 = er[i + 1] + cc[j + 1];
-            const bool ok = c_valid(lc, win, i, j);
+            const bool ok = g_valid<G>(lc, win, i, j);
             const float v = G::CW == 1 ? lerp_col(ay, lerp_row(ax, E[e00], E[e10] - E[e00]),
                                                   lerp_row(ax, E[e01], E[e11] - E[e01]))
                                        : bilerp(w, E[e00], E[e10], E[e01], E[e11]);
@@ -1047,24 +1070,35 @@ __device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_
             }
         }
     }
+    // In an exact build every row of an active lane is valid, and the one
+    // idle lane reads the zero block, so its T, GX and GY come out zero: no
+    // row needs a select
+    if constexpr (G::EXACT)
+        if (lane < 4 * (R + 2)) Tb[(lane >> 2) * TBS + G::ZC + (lane & 3)] = 0.0f;
     wave_lds_sync();
     // the lane's strip: rows a = 0 .. R+1 of Tb around its column, with a
     // three-row sliding window of D = right - left and S = (3 l + 10 c + 3 r) / 32
-    const float *tb = Tb + lc.r0 * TBS + lc.c0;
-    float d0 = 0.0f, d1 = 0.0f, s0 = 0.0f, s1 = 0.0f, c1 = 0.0f;
+    auto strip = [&](const float *tb, auto masked) {
+        constexpr bool MASKED = decltype(masked)::value;
+        float d0 = 0.0f, d1 = 0.0f, s0 = 0.0f, s1 = 0.0f, c1 = 0.0f;
 #pragma unroll
-    for (int a = 0; a < R + 2; ++a) {
-        const float l = tb[a * TBS], c = tb[a * TBS + 1], r = tb[a * TBS + 2];
-        const float d2 = r - l, s2 = fmaf(0.09375f, l + r, 0.3125f * c);
-        if (a >= 2) {
-            const int i = a - 2;
-            const bool ok = c_valid(lc, win, i, 0);
-            T[i][0] = c1;                  // invalid pixels have GX = GY = 0: they add nothing
-            GX[i][0] = ok ? fmaf(0.3125f, d1, 0.09375f * (d0 + d2)) : 0.0f;
-            GY[i][0] = ok ? s2 - s0 : 0.0f;
+        for (int a = 0; a < R + 2; ++a) {
+            const float l = tb[a * TBS], c = tb[a * TBS + 1], r = tb[a * TBS + 2];
+            const float d2 = r - l, s2 = fmaf(0.09375f, l + r, 0.3125f * c);
+            if (a >= 2) {
+                const int i = a - 2;
+                const bool ok = !MASKED || c_valid(lc, win, i, 0);
+                T[i][0] = c1;              // invalid pixels have GX = GY = 0: they add nothing
+                GX[i][0] = ok ? fmaf(0.3125f, d1, 0.09375f * (d0 + d2)) : 0.0f;
+                GY[i][0] = ok ? s2 - s0 : 0.0f;
+            }
+            d0 = d1; d1 = d2; s0 = s1; s1 = s2; c1 = c;
         }
-        d0 = d1; d1 = d2; s0 = s1; s1 = s2; c1 = c;
-    }
+    };
+    if constexpr (G::EXACT)
+        strip(lc.active ? Tb + lc.r0 * TBS + lc.c0 : Tb + G::ZC, std::false_type{});
+    else
+        strip(Tb + lc.r0 * TBS + lc.c0, std::true_type{});
 }
 
 struct PassResult {
@@ -1094,7 +1128,7 @@ __device__ __forceinline__ void finish_level0(const LaneCfg &lc, int win, float 
 #pragma unroll
         for (int i = 0; i < G::R; ++i) {
             const float h1 = lerp_row(ax, jt[i + 1][0], jt[i + 1][1]);
-            acc += c_valid(lc, win, i, 0) ? fabsf(T[i][0] - lerp_col(ay, h0, h1)) : 0.0f;
+            acc += g_valid<G>(lc, win, i, 0) ? fabsf(T[i][0] - lerp_col(ay, h0, h1)) : 0.0f;
             h0 = h1;
         }
     } else {
@@ -1118,7 +1152,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
                                const TrackArgs &a, const LaneCfg &lc, int lane, float *lds, int32_t *iters)
 {
     constexpr int R = G::R, CW = G::CW;
-    const int win = a.win, h = (win - 1) >> 1, L = a.levels;
+    const int win = G::EXACT ? G::WMAX : a.win, h = (win - 1) >> 1, L = a.levels;
     const float nw = (float)(win * win);
     PassResult pr;
     pr.status = LK_OK;
@@ -1446,6 +1480,7 @@ __global__ void k_reset_counters(int *c)
 // Layouts: (CW, R) = (1, 7) for windows up to 21, (1, 16) up to 31,
 // (4, 16) up to 63; each keeps ceil(win/CW) * ceil(win/R) <= 64 lanes.
 using GeoW21 = Geo<1, 7, 21, 4, 4>;
+using GeoW21X = Geo<1, 7, 21, 4, 6, true>;     // win = 21 exactly: 80 registers, 6 wavefronts per SIMD
 using GeoW31 = Geo<1, 16, 31, 4, 2>;
 using GeoW63 = Geo<4, 16, 63, 1, 1>;
 
@@ -1486,7 +1521,9 @@ template <int ST>
 hipError_t launch_track_st(const PyrDesc *prev, const PyrDesc *next, const TrackArgs &a, hipStream_t s)
 {
     switch (choose_layout(a.win)) {
-    case LAYOUT_W21: return launch_track_g<ST, GeoW21>(prev, next, a, s);
+    case LAYOUT_W21:
+        return a.win == GeoW21X::WMAX ? launch_track_g<ST, GeoW21X>(prev, next, a, s)
+                                      : launch_track_g<ST, GeoW21>(prev, next, a, s);
     case LAYOUT_W31: return launch_track_g<ST, GeoW31>(prev, next, a, s);
     default: return launch_track_g<ST, GeoW63>(prev, next, a, s);
     }
@@ -1503,7 +1540,9 @@ template <int ST>
 hipError_t launch_track_batched_st(const BatchItem *items, int n_items, const TrackArgs &a, hipStream_t s)
 {
     switch (choose_layout(a.win)) {
-    case LAYOUT_W21: return launch_track_batched_g<ST, GeoW21>(items, n_items, a, s);
+    case LAYOUT_W21:
+        return a.win == GeoW21X::WMAX ? launch_track_batched_g<ST, GeoW21X>(items, n_items, a, s)
+                                      : launch_track_batched_g<ST, GeoW21>(items, n_items, a, s);
     case LAYOUT_W31: return launch_track_batched_g<ST, GeoW31>(items, n_items, a, s);
     default: return launch_track_batched_g<ST, GeoW63>(items, n_items, a, s);
     }
@@ -1602,7 +1641,7 @@ hipError_t launch_track_persist_st(const BatchItem *items, int n_items, const Tr
                                    int blocks_per_cu, int num_cus, hipStream_t s)
 {
     switch (choose_layout(a.win)) {
-    case LAYOUT_W21:
+    case LAYOUT_W21:      // (the exact build of the persistent kernel would spill at 6 wavefronts per SIMD)
         return launch_track_persist_g<ST, GeoW21>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
     case LAYOUT_W31:
         return launch_track_persist_g<ST, GeoW31>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
