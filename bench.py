@@ -252,9 +252,11 @@ def run_batched(args):
     best, tuned_ms = lk.lk_batch_tune(step, reps=3)
     log("autotuner: persistent=%d blocks_per_cu=%d (%.3f ms/step while tuning)" %
         (best.persistent, best.blocks_per_cu, tuned_ms))
-    # the tracker alone, same shape, for the roofline of the dominant kernel
+    # the tracker alone, same shape, for the roofline of the dominant kernel:
+    # direct launches back to back (a graph replay per launch would add its
+    # own gap to every kernel)
     trk = lk.lk_batch_create(ctx, [], [], wl.pairs, wl.pts, None, wl.params, wl.out, wl.st, wl.res, None,
-                             config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 1, 0))
+                             config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 0, 0))
     t_trk = time_block(lambda: lk.lk_batch_run(trk), max(args.steps, 10), args.warmup)
     t_pyr = wl.time_build(max(args.steps, 10), args.warmup)
     wall, per = time_steps(lambda: lk.lk_batch_run(step), args.steps, args.warmup)
@@ -934,7 +936,7 @@ def run_sweep(args):
                                       None, config=lk.lk_exec_config(0, 4, 1, 0))
             best, _ = lk.lk_batch_tune(step, reps=3)
             trk = lk.lk_batch_create(ctx, [], [], pairs, pts, None, wl.params, out, st, res, None,
-                                     config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 1, 0))
+                                     config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 0, 0))
             t_trk = time_block(lambda: lk.lk_batch_run(trk), reps, args.warmup)
             t_step = time_block(lambda: lk.lk_batch_run(step), reps, args.warmup)
 
