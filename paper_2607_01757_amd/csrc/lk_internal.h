@@ -49,7 +49,8 @@ struct BatchItem {
     const int32_t *limit;      // nullable: only the first *limit of the n points are live (a count on the device)
 };
 
-// A descriptor to be copied to device memory by k_write_descs.
+// A descriptor to be copied to device memory (by k_write_descs, or by the
+// first workgroups of the fused level-1/2 pyramid launch).
 struct PyrDescWrite {
     PyrDesc *dst;
     PyrDesc desc;
@@ -182,8 +183,10 @@ hipError_t launch_downsample(const DownJob &job, hipStream_t stream);
 hipError_t launch_downsample_batched(const DownJob *d_jobs, const int32_t *d_tile_job, int total_tiles,
                                      hipStream_t stream);
 hipError_t launch_pyr12(const Pyr12Job &job, hipStream_t stream);
+// d_descs / n_descs: descriptor writes folded into the launch (one per
+// workgroup, n_descs <= total_tiles), or nullptr / 0
 hipError_t launch_pyr12_batched(const Pyr12Job *d_jobs, const int32_t *d_tile_job, int total_tiles,
-                                hipStream_t stream);
+                                const PyrDescWrite *d_descs, int n_descs, hipStream_t stream);
 hipError_t launch_grad(const GradJob &job, hipStream_t stream);
 hipError_t launch_grad_batched(const GradJob *d_jobs, const int32_t *d_tile_job, int total_tiles,
                                hipStream_t stream);

@@ -449,9 +449,19 @@ __global__ __launch_bounds__(kThreads) void k_pyr12(Pyr12Job j)
     else pyr12_tile<false>(j, tile, sm);
 }
 
-__global__ __launch_bounds__(kThreads) void k_pyr12_batched(const Pyr12Job *jobs, const int32_t *tile_job)
+__global__ __launch_bounds__(kThreads) void k_pyr12_batched(const Pyr12Job *jobs, const int32_t *tile_job,
+                                                            const PyrDescWrite *descs, int n_descs)
 {
     __shared__ P12Smem sm;
+    // the device descriptors of the pyramids being built, one per workgroup of
+    // the first n_descs (only launches after this one read them); this saves
+    // the descriptor-write launch of a build
+    if ((int)blockIdx.x < n_descs) {
+        static_assert(sizeof(PyrDesc) % 4 == 0, "descriptor copied as words");
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&descs[blockIdx.x].desc);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(descs[blockIdx.x].dst);
+        for (int i = threadIdx.x; i < (int)(sizeof(PyrDesc) / 4); i += kThreads) dst[i] = src[i];
+    }
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const Pyr12Job j = jobs[uniform_i(tile_job[tile])];
     if (j.f16) pyr12_tile<true>(j, tile - j.tile_begin, sm);
@@ -1582,10 +1592,12 @@ hipError_t launch_pyr12(const Pyr12Job &job, hipStream_t stream)
 }
 
 hipError_t launch_pyr12_batched(const Pyr12Job *d_jobs, const int32_t *d_tile_job, int total_tiles,
-                                hipStream_t stream)
+                                const PyrDescWrite *d_descs, int n_descs, hipStream_t stream)
 {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pyr12_batched, dim3(total_tiles), dim3(kThreads), 0, stream, d_jobs, d_tile_job);
+    if (n_descs > total_tiles) return hipErrorInvalidValue;      // one descriptor per workgroup at most
+    hipLaunchKernelGGL(k_pyr12_batched, dim3(total_tiles), dim3(kThreads), 0, stream, d_jobs, d_tile_job, d_descs,
+                       n_descs);
     return hipGetLastError();
 }
 

@@ -530,10 +530,16 @@ void BuildTables::pack(char *host) const
 
 hipError_t launch_build_tables(const BuildTables &t, const char *d_base, hipStream_t s)
 {
-    hipError_t e = launch_write_descs(reinterpret_cast<const PyrDescWrite *>(d_base), (int)t.descs.size(), s);
+    // the descriptor writes ride on the fused level-1/2 launch when it has a
+    // workgroup for each of them, else they take a launch of their own
+    const PyrDescWrite *d_descs = reinterpret_cast<const PyrDescWrite *>(d_base);
+    const int nd = (int)t.descs.size();
+    const bool fold = !t.p12.empty() && nd <= (int)t.tj_p12.size();
+    hipError_t e = fold ? hipSuccess : launch_write_descs(d_descs, nd, s);
     if (e == hipSuccess && !t.p12.empty())
         e = launch_pyr12_batched(reinterpret_cast<const Pyr12Job *>(d_base + t.off_p12),
-                                 reinterpret_cast<const int32_t *>(d_base + t.off_tj_p12), (int)t.tj_p12.size(), s);
+                                 reinterpret_cast<const int32_t *>(d_base + t.off_tj_p12), (int)t.tj_p12.size(),
+                                 fold ? d_descs : nullptr, fold ? nd : 0, s);
     for (int l = 1; l < LK_MAX_LEVELS && e == hipSuccess; ++l)
         if (!t.down[l].empty())
             e = launch_downsample_batched(reinterpret_cast<const DownJob *>(d_base + t.off_down[l]),
