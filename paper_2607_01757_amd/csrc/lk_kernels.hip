@@ -11,16 +11,16 @@
 // pixels of a row (coalesced) and each lane reuses bilinear taps between its
 // vertically adjacent pixels.  Because the window offsets are integers, every
 // pixel of the window shares one set of bilinear weights, so a lane holds the
-// raw taps of the target frame in registers and only reloads them when the
+// taps of the target frame in registers (as left tap and right-minus-left
+// difference in the one-column layouts) and only reloads them when the
 // integer part of the estimate moves.  Sums over the window (the 2x2 normal
-// matrix and the mismatch vector) are reduced with DPP row operations, one
-// swizzle and two lane reads, in a fixed order: every lane obtains the same
-// bits, control flow stays wave-uniform, and a point's result does not depend
-// on what else is in the launch.  No MFMA: nothing here is a dense
+// matrix and the mismatch vector) are reduced with DPP adds and one lane read
+// in a fixed order: every lane obtains the same bits, control flow stays
+// wave-uniform, and a point's result does not depend on what else is in the
+// launch.  No MFMA: nothing here is a dense
 // contraction.
 #include "lk_internal.h"
 
-#include <climits>
 #include <type_traits>
 
 namespace lkmi {
