@@ -135,3 +135,36 @@ def test_invalid_batch_arguments(lk, ctx):
     with pytest.raises(lk.LKError):
         lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, bad, *out)
     st.close()
+
+
+@pytest.mark.parametrize("levels_of", [[2, 2, 2, 3, 2, 2, 2], [3, 3, 3, 3, 3, 3, 3]])
+def test_batched_build_writes_every_descriptor(lk, ctx, levels_of):
+    """A batched build writes each pyramid's device descriptor either with the
+    fused level-1/2 launch (one per workgroup, when it has a workgroup for
+    each) or with a launch of its own (here: 2-level pyramids have no fused
+    job, so the first case has more descriptors than fused workgroups).  The
+    tracker reads those descriptors: tracking on the batch-built pyramids must
+    equal tracking on singly built ones, bit for bit."""
+    import torch
+    streams = synth.batch_streams(21, n_streams=len(levels_of), kp_range=(20, 120),
+                                  resolutions=((97, 131), (160, 120)))
+    prev = [torch.from_numpy(s.prev).cuda() for s in streams]
+    nxt = [torch.from_numpy(s.next).cuda() for s in streams]
+    mk = lambda: [lk.lk_pyramid_create(ctx, s.width, s.height, L, 0) for s, L in zip(streams, levels_of)]
+    pp, pn, qn = mk(), mk(), mk()
+    lk.lk_build_pyramids(ctx, pp, prev)
+    lk.lk_build_pyramids(ctx, pn, nxt)                   # batched
+    for q, im in zip(qn, nxt):
+        lk.lk_build_pyramid(ctx, q, im)                  # one at a time
+    params = lk.make_params(21, 2, 30, 0.01, 1e-6, 0.0)
+    for a, b, q, s in zip(pp, pn, qn, streams):
+        n = len(s.pts)
+        pts = torch.from_numpy(s.pts).cuda()
+        got, ref = lk.outputs(n, 2, with_iters=True), lk.outputs(n, 2, with_iters=True)
+        lk.lk_track(ctx, a, b, pts, None, n, params, *got)
+        lk.lk_track(ctx, a, q, pts, None, n, params, *ref)
+        torch.cuda.synchronize()
+        same([t.cpu().numpy() for t in ref], [t.cpu().numpy() for t in got])
+        assert (ref[1].cpu().numpy() == 0).mean() > 0.5
+    for p in pp + pn + qn:
+        lk.lk_pyramid_destroy(p)
