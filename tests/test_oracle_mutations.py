@@ -53,6 +53,25 @@ MUTANTS = [
      "    return LKO_OK;"),
     ("binary16 rounding truncates", "double r = nearbyint(x / q) * q;", "double r = trunc(x / q) * q;"),
     ("guess scaled to the wrong level", "double sc = ldexp(1.0, -(L - 1));", "double sc = ldexp(1.0, -L);"),
+    # the decision margins (they decide which points the GPU parity rule treats as near a threshold)
+    ("convergence margin from the last step only", "if (mc < m->conv) m->conv = mc;", "m->conv = mc;"),
+    ("convergence margin in px instead of relative to eps", "double mc = fabs(nrm / prm->eps - 1.0);",
+     "double mc = fabs(nrm - prm->eps);"),
+    ("out-of-bounds margin of a level in level-0 px",
+     "double bd = box_dist(qx, qy, -h, W - 1.0 + h, H - 1.0 + h);\n            if (fabs(bd) < m->oob) m->oob = fabs(bd);",
+     "double bd = box_dist(qx, qy, -h, W - 1.0 + h, H - 1.0 + h);\n"
+     "            if (fabs(bd) / sc < m->oob) m->oob = fabs(bd) / sc;"),
+    ("out-of-bounds margin against the image box on every level",
+     "double bd = box_dist(qx, qy, -h, W - 1.0 + h, H - 1.0 + h);\n            if (fabs(bd) < m->oob) m->oob = fabs(bd);",
+     "double bd = box_dist(qx, qy, -h, W - 1.0 + h, H - 1.0 + h);\n"
+     "            { double bi = box_dist(qx, qy, 0.0, W - 1.0, H - 1.0); if (fabs(bi) < m->oob) m->oob = fabs(bi); }"),
+    ("out-of-bounds margin of the final check dropped",
+     "double bd = box_dist(qx, qy, 0.0, J->w[0] - 1.0, J->h[0] - 1.0);\n    if (fabs(bd) < m->oob) m->oob = fabs(bd);",
+     "double bd = box_dist(qx, qy, 0.0, J->w[0] - 1.0, J->h[0] - 1.0);"),
+    ("forward-backward margin measured from q", "m.fb = fabs(fbd - prm->fb_thresh);",
+     "m.fb = fabs(sqrt((bx - qx) * (bx - qx) + (by - qy) * (by - qy)) - prm->fb_thresh);"),
+    ("forward-backward margin relative", "m.fb = fabs(fbd - prm->fb_thresh);", "m.fb = fabs(fbd / prm->fb_thresh - 1.0);"),
+    ("eigenvalue margin absolute", "double me = fabs(meig / prm->min_eig - 1.0);", "double me = fabs(meig - prm->min_eig);"),
 ]
 
 GFTT_MUTANTS = [
@@ -71,7 +90,8 @@ GFTT_MUTANTS = [
     ("gftt border not applied", "for (int y = border; y < h - border; ++y)", "for (int y = 0; y < h; ++y)"),
 ]
 
-PINS = ["tests/test_oracle_primitives.py", "tests/test_oracle_tracker.py", "tests/test_oracle_gftt.py"]
+PINS = ["tests/test_oracle_primitives.py", "tests/test_oracle_tracker.py", "tests/test_oracle_margins.py",
+        "tests/test_oracle_cross.py", "tests/test_oracle_gftt.py"]
 
 # planted in a copy of oracle/pool.py (the track-pool lifecycle)
 POOL_SRC = os.path.join(ROOT, "oracle", "pool.py")
