@@ -82,16 +82,22 @@ def check_streams(streams, res, offs, counts, *, win=21, levels=3, f16=False):
     n_ok = 0
     worst = 0.0
     errs64 = []
+    cls = np.zeros(3, np.int64)
     for s, o, c in zip(streams, offs, counts):
         g = tuple(x[o:o + c] for x in res)
         r = oracle.track(s.prev, s.next, s.pts, win=win, levels=levels, min_eig=1e-6, f16=f16, nthreads=THREADS)
         rep = compare(*g, r)
         n_ok += rep.compared_ok
         worst = max(worst, rep.max_err)
+        cls += (rep.n_near, rep.n_capped, rep.n_unstable)
         if f16:
             r64 = oracle.track(s.prev, s.next, s.pts, win=win, levels=levels, min_eig=1e-6, nthreads=THREADS)
             both = (g[1] == 0) & (r64.status == 0)
             errs64.append(np.abs(g[0][both] - r64.pts[both]).max(axis=1))
+    n = int(sum(counts))
+    print("points outside the strict class: near %d, capped %d (of %d, %.2f%%)"
+          % (cls[0], cls[1], n, 100.0 * cls.sum() / n))
+    assert cls.sum() <= 0.03 * n
     return n_ok, worst, (np.concatenate(errs64) if errs64 else None)
 
 
@@ -108,7 +114,7 @@ def test_batched_workload_all_keypoints_f16(lk, ctx, streams64):
     print("binary16: %d compared with the binary16 oracle (max %.3g px); vs FP64: max %.4g p99 %.4g px"
           % (n_ok, worst, e64.max(), np.percentile(e64, 99)))
     assert n_ok >= 0.9 * sum(counts)
-    assert np.percentile(e64, 99) <= 1e-2
+    assert e64.max() <= 1e-2
 
 
 @pytest.mark.parametrize("res_wh,kp", [((1920, 1080), 1500), ((640, 480), 160), ((1920, 1080), 160),

@@ -123,6 +123,7 @@ def test_single_pair_workload_fp32(gt, seed):
     rep = compare(*g, r)
     print("seed", seed, rep)
     assert rep.compared_ok >= 100
+    assert rep.nonstrict_share <= 0.05
 
 
 @pytest.mark.parametrize("t", [5, 400])
@@ -139,6 +140,7 @@ def test_stereo_sequence_fp32_with_fb(gt, t):
         rep = compare(*g, r, r_perturbed=rp)
         print(t, rep)
         assert rep.compared_ok >= 100
+        assert rep.nonstrict_share <= 0.10
 
 
 def test_stereo_sequence_independent_gains_stress(gt):
@@ -151,7 +153,10 @@ def test_stereo_sequence_independent_gains_stress(gt):
     g = gt.track(a, b, pts, levels=4, fb_thresh=1.0)
     r = oracle.track(a, b, pts, levels=4, fb_thresh=1.0, min_eig=1e-6)
     rp = oracle.track(a, b, pts.astype(np.float64) + 1e-5, levels=4, fb_thresh=1.0, min_eig=1e-6)
-    print(compare(*g, r, r_perturbed=rp))
+    rep = compare(*g, r, r_perturbed=rp)
+    print(rep)
+    # many points hit the iteration cap here: they are compared in the capped class
+    assert rep.compared_ok + rep.n_capped >= 100
 
 
 def test_identical_frames_bitwise_zero_flow(gt):
@@ -172,9 +177,8 @@ def test_constant_frame_lost_eig(gt):
     assert np.all(st == 1)
 
 
-W63_SKIP = ("windows above 31 (the four-column lane layout) faulted the GPU (memory aperture violation) in a build "
-            "whose lane-strip template and tap-region loader were changed; the cause is not found yet, so the "
-            "layout's tests stay off the GPU")
+W63_SKIP = ("windows above 31 are rejected by every entry point: the four-column lane layout they need faulted the "
+            "GPU (memory aperture violation) in an earlier build and no cause was shown, so it is not built")
 
 
 @pytest.mark.parametrize("win", [3, 5, 7, 9, 15, 19, 21, 23, 27, 31,
@@ -188,6 +192,48 @@ def test_window_sizes(gt, win):
     r = oracle.track(p.prev, p.next, p.pts, win=win, levels=levels, min_eig=1e-6)
     rep = compare(*g, r)
     print(win, rep)
+    assert rep.compared_ok >= 40
+
+
+def test_windows_above_31_rejected_everywhere(lk, ctx, gt):
+    """Every entry point that takes tracker parameters refuses win > 31 on
+    the host, before anything is enqueued (no kernel runs)."""
+    import torch
+    p = synth.pair(40, 160, 120, 8)
+    pa, ta = gt.pyramid(p.prev, 3, 0)
+    pb, tb = gt.pyramid(p.next, 3, 0)
+    pts = torch.from_numpy(p.pts).cuda()
+    out, st, res, _ = lk.outputs(8, 3)
+    for win in (33, 41, 63):
+        prm = lk.make_params(win=win)
+        with pytest.raises(lk.LKError) as e:
+            lk.lk_track(ctx, pa, pb, pts, None, 8, prm, out, st, res)
+        assert e.value.code == lk.LK_ERR_INVALID_ARG
+        with pytest.raises(lk.LKError) as e:
+            lk.lk_track_batched(ctx, [(pa, pb, 0, 8)], pts, None, prm, out, st, res)
+        assert e.value.code == lk.LK_ERR_INVALID_ARG
+        with pytest.raises(lk.LKError) as e:
+            lk.lk_batch_create(ctx, [], [], [(pa, pb, 0, 8)], pts, None, prm, out, st, res)
+        assert e.value.code == lk.LK_ERR_INVALID_ARG
+        with pytest.raises(lk.LKError) as e:
+            lk.lk_server_create(ctx, lk.server_config(max_streams=2, max_points=16, levels=3, storage=0, params=prm))
+        assert e.value.code == lk.LK_ERR_INVALID_ARG
+    lk.lk_pyramid_destroy(pa)
+    lk.lk_pyramid_destroy(pb)
+
+
+def test_batch_point_offsets_beyond_int32_indexing_rejected(lk, ctx, gt):
+    import torch
+    p = synth.pair(41, 160, 120, 8)
+    pa, ta = gt.pyramid(p.prev, 3, 0)
+    pb, tb = gt.pyramid(p.next, 3, 0)
+    pts = torch.from_numpy(p.pts).cuda()
+    out, st, res, _ = lk.outputs(8, 3)
+    with pytest.raises(lk.LKError) as e:
+        lk.lk_track_batched(ctx, [(pa, pb, (1 << 30) - 4, 8)], pts, None, lk.make_params(), out, st, res)
+    assert e.value.code == lk.LK_ERR_INVALID_ARG and "2^30" in str(e.value)
+    lk.lk_pyramid_destroy(pa)
+    lk.lk_pyramid_destroy(pb)
 
 
 @pytest.mark.parametrize("levels", [1, 2, 5])
@@ -195,7 +241,9 @@ def test_level_counts(gt, levels):
     p = synth.pair(30 + levels, 320, 256, 80, max_shift=1.5 if levels == 1 else 8.0)
     g = gt.track(p.prev, p.next, p.pts, levels=levels)
     r = oracle.track(p.prev, p.next, p.pts, levels=levels, min_eig=1e-6)
-    print(levels, compare(*g, r))
+    rep = compare(*g, r)
+    print(levels, rep)
+    assert rep.compared_ok >= 50
 
 
 def test_tiny_frame_coarsest_level_4px(gt):
@@ -268,5 +316,6 @@ def test_f16_storage_matches_f16_oracle(gt, t):
     r64 = oracle.track(a, b, pts, win=31, levels=4, fb_thresh=1.0, min_eig=1e-6)
     both = (g[1] == 0) & (r64.status == 0)
     err = np.abs(g[0][both] - r64.pts[both]).max(axis=1)
-    print("f16 vs fp64-oracle: max %.4g p99 %.4g" % (err.max(), np.percentile(err, 99)))
-    assert np.percentile(err, 99) <= 1e-2
+    print("f16 vs fp64-oracle: %d points, max %.4g p99 %.4g" % (both.sum(), err.max(), np.percentile(err, 99)))
+    assert both.sum() >= 100
+    assert err.max() <= 1e-2
