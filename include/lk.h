@@ -82,13 +82,14 @@ enum {
 enum { LK_OK = 0, LK_LOST_EIG = 1, LK_LOST_OOB = 2, LK_LOST_FB = 3 };
 
 #define LK_MAX_LEVELS 8
+#define LK_MAX_WIN 31          /* largest window side the tracker kernels are built for */
 
 typedef struct lk_context lk_context;
 typedef struct lk_pyramid lk_pyramid;
 typedef struct lk_server lk_server;
 typedef void *lk_stream;              /* hipStream_t */
 
-/* Tracker parameters.  Valid ranges: win odd in [3, 63]; levels in
+/* Tracker parameters.  Valid ranges: win odd in [3, LK_MAX_WIN]; levels in
  * [1, pyramid levels]; max_iters in [1, 1000]; eps > 0; min_eig >= 0;
  * fb_thresh >= 0 (0 disables the forward-backward check); use_guess 0 or 1.
  * Defaults (lk_params_default): 21, 3, 30, 0.01, 1e-6, 0, 0. */
@@ -104,6 +105,12 @@ typedef struct {
 } lk_params;
 
 lk_params lk_params_default(void);
+
+/* Checks params against the ranges above for pyramids of pyr_levels levels
+ * (1..LK_MAX_LEVELS): LK_SUCCESS, or LK_ERR_INVALID_ARG with the reason in
+ * lk_last_error().  Every entry point that takes lk_params applies the same
+ * check before it enqueues anything; this one needs no device. */
+lk_result lk_params_check(const lk_params *params, int32_t pyr_levels);
 
 /* Human-readable message of the last failed call on this thread ("" if none). */
 const char *lk_last_error(void);
@@ -446,6 +453,12 @@ lk_result lk_server_poll(lk_server *srv, uint64_t ticket, float *h_out_pts, uint
  * tickets become unknown) and frees its resources. */
 lk_result lk_server_close_stream(lk_server *srv, uint32_t id);
 lk_result lk_server_get_stats(lk_server *srv, lk_server_stats *out);
+/* Fault injection for tests of the failure path: the next n launches fail on
+ * the host while staging their tables (after their frames' copies were
+ * enqueued).  Their frames complete with LK_ERR_DEVICE from lk_server_poll;
+ * each stream keeps its previous pyramid, so its next frame is tracked from
+ * its last completed frame.  n = 0 clears it. */
+lk_result lk_server_fail_next_launches(lk_server *srv, int32_t n);
 void lk_server_destroy(lk_server *srv);
 
 #ifdef __cplusplus

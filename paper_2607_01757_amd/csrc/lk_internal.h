@@ -173,7 +173,7 @@ constexpr int kGradTileW = 64, kGradTileH = 16;
 constexpr int kP12TileW = 32, kP12TileH = 16;   // level-2 tile of the fused build
 
 // Window-to-lane layouts of the tracker (see lk_kernels.hip).
-enum Layout { LAYOUT_W21 = 0, LAYOUT_W31 = 1, LAYOUT_W63 = 2 };
+enum Layout { LAYOUT_NONE = -1, LAYOUT_W21 = 0, LAYOUT_W31 = 1 };
 int choose_layout(int win);
 
 // Launchers (lk_kernels.hip).  All enqueue on `stream` and return the launch status.

@@ -1487,8 +1487,8 @@ __global__ void k_reset_counters(int *c)
     if (threadIdx.x < 8) c[threadIdx.x] = 0;
 }
 
-// Layouts: (CW, R) = (1, 7) for windows up to 21, (1, 16) up to 31,
-// (4, 16) up to 63; each keeps ceil(win/CW) * ceil(win/R) <= 64 lanes.
+// Layouts: (CW, R) = (1, 7) for windows up to 21, (1, 16) up to 31; each
+// keeps ceil(win/CW) * ceil(win/R) <= 64 lanes.
 // The 21x21 layouts run one wavefront per workgroup: keypoints take different
 // numbers of iterations, and a workgroup's LDS is released only when its last
 // wavefront ends, so larger workgroups hold idle LDS (measured on the 64-stream
@@ -1497,7 +1497,6 @@ __global__ void k_reset_counters(int *c)
 using GeoW21 = Geo<1, 7, 21, 1, 4>;
 using GeoW21X = Geo<1, 7, 21, 1, 6, true>;     // win = 21 exactly: 80 registers, 6 wavefronts per SIMD
 using GeoW31 = Geo<1, 16, 31, 4, 2>;
-using GeoW63 = Geo<4, 16, 63, 1, 1>;
 
 // Copies pyramid descriptors into device memory, in stream order.
 __global__ void k_write_desc(PyrDesc *dst, PyrDesc src) { if (threadIdx.x == 0) *dst = src; }
@@ -1540,7 +1539,7 @@ hipError_t launch_track_st(const PyrDesc *prev, const PyrDesc *next, const Track
         return a.win == GeoW21X::WMAX ? launch_track_g<ST, GeoW21X>(prev, next, a, s)
                                       : launch_track_g<ST, GeoW21>(prev, next, a, s);
     case LAYOUT_W31: return launch_track_g<ST, GeoW31>(prev, next, a, s);
-    default: return launch_track_g<ST, GeoW63>(prev, next, a, s);
+    default: return hipErrorInvalidValue;      // no layout for this window
     }
 }
 
@@ -1559,19 +1558,19 @@ hipError_t launch_track_batched_st(const BatchItem *items, int n_items, const Tr
         return a.win == GeoW21X::WMAX ? launch_track_batched_g<ST, GeoW21X>(items, n_items, a, s)
                                       : launch_track_batched_g<ST, GeoW21>(items, n_items, a, s);
     case LAYOUT_W31: return launch_track_batched_g<ST, GeoW31>(items, n_items, a, s);
-    default: return launch_track_batched_g<ST, GeoW63>(items, n_items, a, s);
+    default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-// Window side -> lane layout: (CW, R) = (1, 7) up to 21, (1, 16) up to 31,
-// (4, 16) up to 63; each keeps ceil(win/CW) * ceil(win/R) <= 64 lanes.
+// Window side -> lane layout: (CW, R) = (1, 7) up to 21, (1, 16) up to 31;
+// LAYOUT_NONE above (the host rejects such windows before any launch).
 int choose_layout(int win)
 {
     if (win <= 21) return LAYOUT_W21;
-    if (win <= 31) return LAYOUT_W31;
-    return LAYOUT_W63;
+    if (win <= LK_MAX_WIN) return LAYOUT_W31;
+    return LAYOUT_NONE;
 }
 
 hipError_t launch_downsample(const DownJob &job, hipStream_t stream)
@@ -1663,7 +1662,7 @@ hipError_t launch_track_persist_st(const BatchItem *items, int n_items, const Tr
     case LAYOUT_W31:
         return launch_track_persist_g<ST, GeoW31>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
     default:
-        return launch_track_persist_g<ST, GeoW63>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
+        return hipErrorInvalidValue;
     }
 }
 

@@ -101,8 +101,10 @@ int level_dims(int w, int h, int levels, int32_t *ws, int32_t *hs)
 lk_result check_params(const lk_params *p, int pyr_levels)
 {
     if (!p) return fail(LK_ERR_INVALID_ARG, "params is NULL");
-    if (p->win < 3 || p->win > 63 || (p->win & 1) == 0)
-        return fail(LK_ERR_INVALID_ARG, "win must be odd in [3, 63] (got %d)", p->win);
+    // windows above 31 would need the four-column lane layout, which is not
+    // built (an earlier build of it faulted on the GPU and no cause was shown)
+    if (p->win < 3 || p->win > LK_MAX_WIN || (p->win & 1) == 0)
+        return fail(LK_ERR_INVALID_ARG, "win must be odd in [3, %d] (got %d)", LK_MAX_WIN, p->win);
     if (p->levels < 1 || p->levels > pyr_levels)
         return fail(LK_ERR_INVALID_ARG, "levels must be in [1, %d] (got %d)", pyr_levels, p->levels);
     if (p->max_iters < 1 || p->max_iters > 1000)
@@ -176,6 +178,15 @@ void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<D
 // ====================================================================== ABI
 
 extern "C" {
+
+lk_result lk_params_check(const lk_params *params, int32_t pyr_levels)
+{
+    if (pyr_levels < 1 || pyr_levels > LK_MAX_LEVELS)
+        return fail(LK_ERR_INVALID_ARG, "pyr_levels must be in [1, %d] (got %d)", LK_MAX_LEVELS, pyr_levels);
+    lk_result r = check_params(params, pyr_levels);
+    if (r == LK_SUCCESS) clear_error();
+    return r;
+}
 
 lk_params lk_params_default(void)
 {
@@ -450,6 +461,9 @@ lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const l
         if (r != LK_SUCCESS) return r;
         if (p.n < 0 || p.pt_offset < 0 || p.reserved != 0)
             return fail(LK_ERR_INVALID_ARG, "pair %d: negative n or offset, or reserved != 0", i);
+        // the kernels index points with 32-bit integers (2 idx + 1 < 2^31)
+        if (p.pt_offset + (int64_t)p.n > (int64_t(1) << 30))
+            return fail(LK_ERR_INVALID_ARG, "pair %d: pt_offset + n exceeds 2^30", i);
         if (*storage >= 0 && p.prev->desc.storage != *storage)
             return fail(LK_ERR_INVALID_ARG, "pair %d: all pairs of one batch must share a storage", i);
         *storage = p.prev->desc.storage;

@@ -19,15 +19,16 @@ LK_ERR_BUSY, LK_ERR_NOT_READY, LK_ERR_NOT_FOUND, LK_ERR_NOT_IMPLEMENTED = 4, 5, 
 LK_STORAGE_F32, LK_STORAGE_F16 = 0, 1
 LK_OK, LK_LOST_EIG, LK_LOST_OOB, LK_LOST_FB = 0, 1, 2, 3
 LK_MAX_LEVELS = 8
+LK_MAX_WIN = 31
 
 # Every symbol include/lk.h declares (checked by the CPU tests).
 ABI_SYMBOLS = (
-    "lk_params_default", "lk_last_error", "lk_context_create", "lk_context_destroy",
+    "lk_params_default", "lk_params_check", "lk_last_error", "lk_context_create", "lk_context_destroy",
     "lk_context_bytes_in_use", "lk_pyramid_create", "lk_pyramid_destroy", "lk_pyramid_info",
     "lk_build_pyramid", "lk_build_pyramids", "lk_pyramid_read_level", "lk_track", "lk_track_batched",
     "lk_batch_create", "lk_batch_run", "lk_batch_tune", "lk_batch_config", "lk_batch_destroy",
     "lk_server_create", "lk_server_open_stream", "lk_server_submit", "lk_server_poll", "lk_server_close_stream",
-    "lk_server_get_stats", "lk_server_destroy",
+    "lk_server_get_stats", "lk_server_fail_next_launches", "lk_server_destroy",
     "lk_detector_create", "lk_detect_corners", "lk_detector_destroy",
     "lk_pool_create", "lk_pool_step", "lk_pool_reset", "lk_pool_destroy",
     "lk_epipolar_check",
@@ -121,6 +122,7 @@ def _load():
     res = C.c_int
     sig = {
         "lk_params_default": (lk_params, []),
+        "lk_params_check": (res, [C.POINTER(lk_params), i32]),
         "lk_last_error": (C.c_char_p, []),
         "lk_context_create": (res, [i32, u64, C.POINTER(vp)]),
         "lk_context_destroy": (None, [vp]),
@@ -145,6 +147,7 @@ def _load():
         "lk_server_poll": (res, [vp, C.c_uint64, vp, vp, vp, C.POINTER(i32), C.POINTER(lk_timing)]),
         "lk_server_close_stream": (res, [vp, C.c_uint32]),
         "lk_server_get_stats": (res, [vp, C.POINTER(lk_server_stats)]),
+        "lk_server_fail_next_launches": (res, [vp, i32]),
         "lk_server_destroy": (None, [vp]),
         "lk_detector_create": (res, [vp, i32, C.c_int64, C.POINTER(vp)]),
         "lk_detect_corners": (res, [vp, C.POINTER(lk_gftt_frame), i32, C.POINTER(lk_gftt_params), vp]),
@@ -187,6 +190,10 @@ def _stream(stream):
 
 def lk_params_default() -> lk_params:
     return lib.lk_params_default()
+
+
+def lk_params_check(params: lk_params, pyr_levels: int):
+    _check(lib.lk_params_check(C.byref(params), pyr_levels))
 
 
 def lk_last_error() -> str:
@@ -356,6 +363,10 @@ def lk_server_get_stats(srv) -> lk_server_stats:
     st = lk_server_stats()
     _check(lib.lk_server_get_stats(srv, C.byref(st)))
     return st
+
+
+def lk_server_fail_next_launches(srv, n: int):
+    _check(lib.lk_server_fail_next_launches(srv, n))
 
 
 def lk_server_destroy(srv):

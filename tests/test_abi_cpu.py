@@ -61,3 +61,31 @@ def test_struct_sizes_match_the_header(lk):
     assert C.sizeof(lk.lk_pair) == 32
     assert C.sizeof(lk.lk_exec_config) == 16
     assert C.sizeof(lk.lk_timing) == 24
+
+
+def test_params_check_window_range(lk):
+    """Odd windows 3..31 pass; even ones, and every window above 31 (the
+    tracker has no lane layout for them), are rejected on the host."""
+    for win in (3, 5, 21, 29, 31):
+        lk.lk_params_check(lk.make_params(win=win), 3)
+    for win in (1, 2, 4, 20, 33, 35, 41, 63, 65):
+        with pytest.raises(lk.LKError) as e:
+            lk.lk_params_check(lk.make_params(win=win), 3)
+        assert e.value.code == lk.LK_ERR_INVALID_ARG
+        assert "win must be odd in [3, 31]" in str(e.value)
+    assert lk.LK_MAX_WIN == 31
+
+
+def test_params_check_other_ranges(lk):
+    good = dict(win=21, levels=3, max_iters=30, eps=0.01, min_eig=1e-6, fb_thresh=1.0)
+    lk.lk_params_check(lk.make_params(**good), 3)
+    bad = [dict(levels=0), dict(levels=4), dict(max_iters=0), dict(max_iters=1001), dict(eps=0.0),
+           dict(eps=float("nan")), dict(min_eig=-1.0), dict(fb_thresh=-0.5), dict(fb_thresh=float("inf"))]
+    for b in bad:
+        with pytest.raises(lk.LKError) as e:
+            lk.lk_params_check(lk.make_params(**dict(good, **b)), 3)
+        assert e.value.code == lk.LK_ERR_INVALID_ARG, b
+    with pytest.raises(lk.LKError):
+        lk.lk_params_check(lk.make_params(**good), 0)
+    with pytest.raises(lk.LKError):
+        lk.lk_params_check(lk.make_params(**good), 9)
