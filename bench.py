@@ -459,98 +459,156 @@ def run_stereo(args, f16):
     return result
 
 
-def run_serve(args):
-    """256 camera streams with Poisson arrivals (U[20,30] Hz), resolution per
-    stream from the batched set, U[150,1500] keypoints per frame, binary16
-    storage, 31x31, 4 levels, forward-backward 1 px; then the same arrival
-    trace through plain per-frame float32 launches."""
+def _serve_trace(args, literal):
+    import synth
+    res = ((752, 480),) if literal else synth.RESOLUTIONS
+    return synth.ServingTrace(args.seed, n_streams=args.serve_streams,
+                              duration_s=args.serve_warmup + args.serve_seconds, resolutions=res)
+
+
+def serve_run(lk, ctx, trace, pool, pts, args, mode, rate_mult=1.0):
+    """Drives one server with the trace's streams from args.serve_threads
+    submitter threads (streams dealt round-robin; each thread also polls its
+    own tickets).  mode "poisson": every frame is submitted at its scheduled
+    arrival time (the trace compressed by rate_mult); latency = completion
+    minus the scheduled arrival (both CLOCK_MONOTONIC), so submitter lag and
+    busy retries count.  mode "closed": every stream keeps queue_depth frames
+    outstanding for the whole run, which saturates the server; latency =
+    completion minus the submit call's entry.  Returns the served results."""
+    import ctypes as C
     import threading
 
-    import torch
-    import synth
-    from paper_2607_01757_amd import lk
-
     warm, dur = args.serve_warmup, args.serve_seconds
-    trace = synth.ServingTrace(args.seed, n_streams=args.serve_streams, duration_s=warm + dur)
-    pool = synth.FramePool(args.seed)
-    rng = np.random.default_rng(args.seed)
-    pts = [synth.uniform_points(rng, sp.n_kp, sp.width, sp.height) for sp in trace.streams]
-    log("serving trace: %d streams, %d frames over %.0f s" % (len(trace.streams), len(trace.events), warm + dur))
-    ctx = lk.lk_context_create(0, 0)
     prm16 = lk.make_params(31, 4, 30, 0.01, 1e-6, 1.0)
+    qd = 4
     cfg = lk.server_config(max_streams=len(trace.streams), max_points=1500, levels=4, storage=lk.LK_STORAGE_F16,
-                           params=prm16, max_batch=len(trace.streams), inflight=args.serve_inflight, queue_depth=4,
-                           hbm_budget_bytes=64 << 30)
+                           params=prm16, max_batch=len(trace.streams), inflight=args.serve_inflight,
+                           queue_depth=qd, hbm_budget_bytes=64 << 30)
     srv = lk.lk_server_create(ctx, cfg)
     ids = [lk.lk_server_open_stream(srv, sp.width, sp.height) for sp in trace.streams]
-    stats0 = lk.lk_server_get_stats(srv)
-    log("server: %d streams open, %.2f GB resident" % (stats0.open_streams, stats0.resident_bytes / 1e9))
+    resident = lk.lk_server_get_stats(srv).resident_bytes
+    nthr = max(1, min(args.serve_threads, len(trace.streams)))
+    mine = [[sp.stream for sp in trace.streams if sp.stream % nthr == t] for t in range(nthr)]
+    events = [[e for e in trace.events if e[1] % nthr == t] for t in range(nthr)]
+    results = [[] for _ in range(nthr)]        # (arrival_ns or submit_ns, done_ns, n, stream)
+    busy = [0] * nthr
+    t0_ns = time.monotonic_ns() + 50_000_000
+    end_ns = t0_ns + int((warm + dur) * 1e9)
 
-    outstanding = []
-    lock = threading.Lock()
-    done = []
-    stop = [False]
-    out_buf = np.zeros((1500, 2), np.float32)
-    st_buf = np.zeros(1500, np.uint8)
-    rs_buf = np.zeros(1500, np.float32)
-
-    def poller():
-        import ctypes as C
+    def poll_some(tid, outstanding, block):
         n = C.c_int32()
         tm = lk.lk_timing()
-        while not stop[0] or outstanding:
-            with lock:
-                batch = list(outstanding)
-            if not batch:
-                time.sleep(0.0002)
-                continue
-            for t in batch:
-                rc = lk.lib.lk_server_poll(srv, t, out_buf.ctypes.data, st_buf.ctypes.data, rs_buf.ctypes.data,
-                                           C.byref(n), C.byref(tm))
+        out = np.zeros((1500, 2), np.float32)
+        st = np.zeros(1500, np.uint8)
+        rs = np.zeros(1500, np.float32)
+        while True:
+            left = []
+            for (t, ref_ns, sid) in outstanding:
+                rc = lk.lib.lk_server_poll(srv, t, out.ctypes.data, st.ctypes.data, rs.ctypes.data, C.byref(n),
+                                           C.byref(tm))
                 if rc == lk.LK_ERR_NOT_READY:
-                    continue
-                with lock:
-                    outstanding.remove(t)
-                if rc == lk.LK_SUCCESS:
-                    done.append((tm.submit_ns, tm.done_ns, n.value))
+                    left.append((t, ref_ns, sid))
+                elif rc == lk.LK_SUCCESS:
+                    results[tid].append((ref_ns if ref_ns else tm.submit_ns, tm.done_ns, n.value, sid))
+                else:
+                    raise RuntimeError("served frame failed: %d" % rc)
+            outstanding[:] = left
+            if not block or not outstanding:
+                return
             time.sleep(0.0001)
 
-    th = threading.Thread(target=poller, daemon=True)
-    th.start()
-    t0 = time.perf_counter()
-    busy = 0
-    for (ts, sid, k) in trace.events:
-        while time.perf_counter() - t0 < ts:
-            time.sleep(0.00005)
+    def submit(tid, sid, k):
         sp = trace.streams[sid]
         f = pool.frame(sp.width, sp.height, sid, k)
         while True:
             try:
-                t = lk.lk_server_submit(srv, ids[sid], f, pts[sid])
-                break
+                return lk.lk_server_submit(srv, ids[sid], f, pts[sid])
             except lk.LKError as e:
                 if e.code != lk.LK_ERR_BUSY:
                     raise
-                busy += 1
-                time.sleep(0.0002)
-        with lock:
-            outstanding.append(t)
-    stop[0] = True
-    th.join()
-    wall = time.perf_counter() - t0
-    base = min(d[0] for d in done)
-    meas = [d for d in done if d[0] - base >= warm * 1e9 and d[2] > 0]
+                busy[tid] += 1
+                time.sleep(0.0001)
+
+    def poisson_worker(tid):
+        outstanding = []
+        for (ts, sid, k) in events[tid]:
+            arrival = t0_ns + int(ts / rate_mult * 1e9)
+            while time.monotonic_ns() < arrival:
+                poll_some(tid, outstanding, False)
+                time.sleep(0.00005)
+            outstanding.append((submit(tid, sid, k), arrival, sid))
+            if len(outstanding) > 8:
+                poll_some(tid, outstanding, False)
+        poll_some(tid, outstanding, True)
+
+    def closed_worker(tid):
+        outstanding = []
+        nxt = {sid: 0 for sid in mine[tid]}
+        while time.monotonic_ns() < t0_ns:
+            time.sleep(0.0001)
+        while time.monotonic_ns() < end_ns:
+            count = {}
+            for (_, _, sid) in outstanding:
+                count[sid] = count.get(sid, 0) + 1
+            for sid in mine[tid]:
+                if count.get(sid, 0) < qd - 1:
+                    outstanding.append((submit(tid, sid, nxt[sid]), 0, sid))
+                    nxt[sid] += 1
+            poll_some(tid, outstanding, False)
+        poll_some(tid, outstanding, True)
+
+    fn = poisson_worker if mode == "poisson" else closed_worker
+    th = [threading.Thread(target=fn, args=(t,)) for t in range(nthr)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    stats = lk.lk_server_get_stats(srv)
+    lk.lk_server_destroy(srv)
+    done = [d for r in results for d in r]
+    meas = [d for d in done if d[0] - t0_ns >= warm * 1e9 and d[2] > 0]
     lat = [(d[1] - d[0]) / 1e6 for d in meas]
     span = (max(d[1] for d in meas) - min(d[0] for d in meas)) / 1e9
     kp = sum(d[2] for d in meas)
-    stats = lk.lk_server_get_stats(srv)
-    served = {"value": kp / span, "unit": "keypoints/s", "p50_frame_ms": percentile(lat, 50),
-              "p99_frame_ms": percentile(lat, 99), "max_frame_ms": float(max(lat)), "frames": len(meas),
-              "batches": int(stats.batches), "frames_per_batch": stats.frames / max(1, stats.batches),
-              "submit_busy_retries": busy, "wall_s": wall, "dtype": "f16 storage, f32 arithmetic"}
-    log("served: %.3g kp/s p50 %.2f ms p99 %.2f ms, %.1f frames/launch" %
-        (served["value"], served["p50_frame_ms"], served["p99_frame_ms"], served["frames_per_batch"]))
-    lk.lk_server_destroy(srv)
+    return {"value": kp / span, "unit": "keypoints/s", "frames_per_s": len(meas) / span,
+            "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
+            "max_frame_ms": float(max(lat)), "frames": len(meas), "batches": int(stats.batches),
+            "frames_per_batch": stats.frames / max(1, stats.batches), "submit_busy_retries": int(sum(busy)),
+            "submitter_threads": nthr, "resident_GB": resident / 1e9,
+            "latency_from": "scheduled arrival" if mode == "poisson" else "submit call",
+            "mode": mode if mode == "closed" else "poisson x%g" % rate_mult,
+            "dtype": "f16 storage, f32 arithmetic"}
+
+
+def run_serve(args):
+    """256 camera streams with Poisson arrivals (U[20,30] Hz), resolution per
+    stream from the batched set (or all 752x480 with --serve-res literal),
+    U[150,1500] keypoints per frame, binary16 storage, 31x31, 4 levels,
+    forward-backward 1 px: the offered trace, then a saturating closed-loop
+    run (served capacity), then the same arrival trace through plain
+    per-frame float32 launches."""
+    import torch
+    import synth
+    from paper_2607_01757_amd import lk
+
+    literal = args.serve_res == "literal"
+    trace = _serve_trace(args, literal)
+    res_set = ((752, 480),) if literal else synth.RESOLUTIONS
+    pool = synth.FramePool(args.seed, resolutions=res_set)
+    rng = np.random.default_rng(args.seed)
+    pts = [synth.uniform_points(rng, sp.n_kp, sp.width, sp.height) for sp in trace.streams]
+    warm, dur = args.serve_warmup, args.serve_seconds
+    log("serving trace: %d streams, %d frames over %.0f s (%s resolutions)"
+        % (len(trace.streams), len(trace.events), warm + dur, "752x480" if literal else "mixed"))
+    ctx = lk.lk_context_create(0, 0)
+    served = serve_run(lk, ctx, trace, pool, pts, args, "poisson", args.serve_rate_mult)
+    log("served (offered load x%g): %.3g kp/s p50 %.2f ms p99 %.2f ms, %.1f frames/launch, %d busy retries"
+        % (args.serve_rate_mult, served["value"], served["p50_frame_ms"], served["p99_frame_ms"],
+           served["frames_per_batch"], served["submit_busy_retries"]))
+    capacity = serve_run(lk, ctx, trace, pool, pts, args, "closed")
+    log("served capacity (closed loop): %.3g kp/s (%.0f frames/s) p50 %.2f ms p99 %.2f ms, %.1f frames/launch"
+        % (capacity["value"], capacity["frames_per_s"], capacity["p50_frame_ms"], capacity["p99_frame_ms"],
+           capacity["frames_per_batch"]))
 
     # plain per-frame float32 launches driven by the same trace, one frame at a time
     prm32 = lk.make_params(31, 4, 30, 0.01, 1e-6, 1.0)
@@ -563,7 +621,7 @@ def run_serve(args):
         pyr[sp.stream] = [lk.lk_pyramid_create(ctx, sp.width, sp.height, 4, lk.LK_STORAGE_F32) for _ in range(2)]
         dev_frames[sp.stream] = [torch.empty((sp.height, sp.width), dtype=torch.uint8, device="cuda") for _ in range(2)]
         d_pts[sp.stream] = torch.from_numpy(pts[sp.stream]).cuda()
-    for (w, h) in synth.RESOLUTIONS:
+    for (w, h) in res_set:
         pinned[(w, h)] = torch.empty((h, w), dtype=torch.uint8).pin_memory()
     seen = {}
     lat2, kp2, t_first, t_last = [], 0, None, None
@@ -595,23 +653,25 @@ def run_serve(args):
             t_last = tdone
     plain = {"value": kp2 / (t_last - t_first), "unit": "keypoints/s", "p50_frame_ms": percentile(lat2, 50),
              "p99_frame_ms": percentile(lat2, 99), "max_frame_ms": float(max(lat2)), "frames": len(lat2),
-             "dtype": "f32"}
+             "latency_from": "scheduled arrival", "dtype": "f32"}
     log("plain per-frame: %.3g kp/s p50 %.2f ms p99 %.2f ms" % (plain["value"], plain["p50_frame_ms"],
                                                                  plain["p99_frame_ms"]))
     for v in pyr.values():
         for p_ in v:
             lk.lk_pyramid_destroy(p_)
     lk.lk_context_destroy(ctx)
+    span_ms = 1e3 * served["frames"] / max(served["frames_per_s"], 1e-9)
     return {
-        "metric": "tracked keypoints/sec + p50/p99 frame latency (served, 256 Poisson streams)",
+        "metric": "tracked keypoints/sec + p50/p99 frame latency (served, %d Poisson streams)" % len(trace.streams),
         "value": served["value"], "unit": "keypoints/s", "n_gpus": 1, "steps": served["frames"], "warmup": warm,
-        "ms_per_step": 1e3 * span / max(1, served["frames"]), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": span_ms / max(1, served["frames"]), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f16", "data": "synthetic",
-        "config": {"workload": "serving: %d streams, Poisson U[20,30] Hz, resolutions {640x480..1920x1080}, "
-                               "U[150,1500] keypoints, 31x31, 4 levels, FB 1 px, binary16 storage, %g s after %g s "
-                               "warm-up" % (len(trace.streams), dur, warm)},
+        "config": {"workload": "serving: %d streams, Poisson U[20,30] Hz x%g, resolutions %s, U[150,1500] "
+                               "keypoints, 31x31, 4 levels, FB 1 px, binary16 storage, %g s after %g s warm-up"
+                               % (len(trace.streams), args.serve_rate_mult,
+                                  "752x480 (literal reading)" if literal else "{640x480..1920x1080}", dur, warm)},
         "p50_frame_ms": served["p50_frame_ms"], "p99_frame_ms": served["p99_frame_ms"],
-        "served": served, "plain": plain,
+        "served": served, "capacity": capacity, "plain": plain,
     }
 
 
@@ -1013,6 +1073,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-inflight", type=int, default=2)
+    ap.add_argument("--serve-threads", type=int, default=8, help="submitter threads of the serve workload")
+    ap.add_argument("--serve-rate-mult", type=float, default=1.0, help="arrival-rate multiplier (serve workload)")
+    ap.add_argument("--serve-res", choices=["mixed", "literal"], default="mixed",
+                    help="serve workload resolutions: the batched set, or every stream 752x480")
     ap.add_argument("--streams", type=int, default=64)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-streams", type=int, default=64)

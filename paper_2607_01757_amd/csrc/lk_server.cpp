@@ -65,6 +65,7 @@ struct CamStream {
     int cur = 0;              // buffers of the next frame
     bool primed = false;      // pyr[cur ^ 1] holds the previous frame
     bool busy = false;        // a frame is in flight
+    int fillers = 0;          // submits copying into a reserved slot right now
     uint32_t seq = 0;
     std::vector<Slot> slots;
     std::deque<int> fifo;     // queued slot indices
@@ -76,6 +77,7 @@ struct Launch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
+    bool failed = false;                       // some enqueue of this launch failed on the host
     std::vector<std::pair<int, int>> frames;   // (camera stream, slot)
     StagingRing ring;                          // tables of this device stream
 };
@@ -98,6 +100,7 @@ struct lk_server {
     bool stop = false;
     uint64_t resident = 0;
     lk_server_stats stats{};
+    int fail_next = 0;        // launches whose table staging is made to fail (fault injection)
 };
 
 namespace {
@@ -119,13 +122,24 @@ void free_stream(lk_server *s, CamStream &c)
     c = CamStream{};
 }
 
-// Completes launches whose event has fired.  Called with the lock held.
+// Completes launches whose event has fired.  A launch that failed on the
+// host (its completion event may never have been recorded) is completed once
+// the work it did enqueue has drained: its frames fail, and their streams
+// keep their buffers and previous pyramid, so the next frame tracks from the
+// last frame that completed.  Called with the lock held.
 void retire(lk_server *s)
 {
     for (auto &L : s->launches) {
         if (!L.busy) continue;
-        hipError_t q = hipEventQuery(L.done);
-        if (q == hipErrorNotReady) continue;
+        hipError_t q;
+        if (L.failed) {
+            (void)hipStreamSynchronize(L.stream);   // the copies out of the pinned slots have finished
+            q = hipErrorLaunchFailure;
+            L.failed = false;
+        } else {
+            q = hipEventQuery(L.done);
+            if (q == hipErrorNotReady) continue;
+        }
         const uint64_t t = now_ns();
         for (auto &fs : L.frames) {
             CamStream &c = s->cams[fs.first];
@@ -191,7 +205,12 @@ lk_result launch_ready(lk_server *s, Launch &L)
         BuildTables bt;
         make_build_tables(build.data(), (int)build.size(), &bt);
         StagingRing::Slot *rs = nullptr;
-        r = L.ring.acquire(bt.bytes, &rs);
+        if (s->fail_next > 0) {
+            --s->fail_next;
+            r = fail(LK_ERR_OUT_OF_MEMORY, "pyramid table staging failed (injected)");
+        } else {
+            r = L.ring.acquire(bt.bytes, &rs);
+        }
         if (r == LK_SUCCESS) {
             bt.pack(static_cast<char *>(rs->host));
             e = hipMemcpyAsync(rs->dev, rs->host, bt.bytes, hipMemcpyHostToDevice, st);
@@ -231,9 +250,10 @@ lk_result launch_ready(lk_server *s, Launch &L)
                 e = hipMemcpyAsync(sl.residual, s->d_res + base, (size_t)sl.n_out * 4, hipMemcpyDeviceToHost, st);
         }
     }
-    if (e == hipSuccess) e = hipEventRecord(L.done, st);
+    if (e == hipSuccess && r == LK_SUCCESS) e = hipEventRecord(L.done, st);
     L.frames = take;
     L.busy = true;
+    L.failed = e != hipSuccess || r != LK_SUCCESS;
     if (e != hipSuccess) return hip_fail(e, "server launch");
     return r;
 }
@@ -390,12 +410,15 @@ lk_result lk_server_submit(lk_server *s, uint32_t id, const uint8_t *h_frame, in
     if (k < 0) return fail(LK_ERR_BUSY, "stream %u: all %zu staging slots hold frames", id, c.slots.size());
     Slot &sl = c.slots[k];
     sl.state = SLOT_FILLING;
+    ++c.fillers;              // lk_server_close_stream waits for this copy to end
     g.unlock();
     // the slot is reserved: only this call writes it until it is queued
     for (int y = 0; y < c.h; ++y) std::memcpy(sl.frame + (size_t)y * c.w, h_frame + (size_t)y * pitch, c.w);
     if (n > 0) std::memcpy(sl.pts, h_pts, (size_t)n * 8);
     if (n > 0 && h_guess) std::memcpy(sl.guess, h_guess, (size_t)n * 8);
     g.lock();
+    --c.fillers;
+    s->cv.notify_all();
     if (!c.open || c.closing) {
         if (c.open) sl.state = SLOT_FREE;
         return fail(LK_ERR_NOT_FOUND, "stream %u was closed", id);
@@ -444,13 +467,23 @@ lk_result lk_server_close_stream(lk_server *s, uint32_t id)
     if (id >= s->cams.size() || !s->cams[id].open) return fail(LK_ERR_NOT_FOUND, "stream %u is not open", id);
     CamStream &c = s->cams[id];
     c.closing = true;
+    // the running frame has completed and no submit is still copying into
+    // one of the stream's staging slots
     s->cv.wait(g, [&] {
         retire(s);
-        return !c.busy;
+        return !c.busy && c.fillers == 0;
     });
     for (auto it = s->tickets.begin(); it != s->tickets.end();)
         if (it->second.first == (int)id) it = s->tickets.erase(it); else ++it;
     free_stream(s, c);
+    return LK_SUCCESS;
+}
+
+lk_result lk_server_fail_next_launches(lk_server *s, int32_t n)
+{
+    if (!s || n < 0) return fail(LK_ERR_INVALID_ARG, "srv is NULL or n < 0");
+    std::lock_guard<std::mutex> g(s->mu);
+    s->fail_next = n;
     return LK_SUCCESS;
 }
 

@@ -163,3 +163,150 @@ def test_admission_budget_and_errors(lk, ctx):
     assert st.open_streams == 1 and st.resident_bytes <= budget
     lk.lk_server_close_stream(srv, b)
     lk.lk_server_destroy(srv)
+
+
+def plain_track(lk, ctx, a, b, pts, prm, levels, storage):
+    import torch
+    h, w = a.shape
+    pa = lk.lk_pyramid_create(ctx, w, h, levels, storage)
+    pb = lk.lk_pyramid_create(ctx, w, h, levels, storage)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    lk.lk_build_pyramid(ctx, pa, ta)
+    lk.lk_build_pyramid(ctx, pb, tb)
+    d_pts = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda()
+    out, st, res, _ = lk.outputs(len(pts), levels)
+    lk.lk_track(ctx, pa, pb, d_pts, None, len(pts), prm, out, st, res)
+    torch.cuda.synchronize()
+    r = out.cpu().numpy(), st.cpu().numpy(), res.cpu().numpy()
+    lk.lk_pyramid_destroy(pa)
+    lk.lk_pyramid_destroy(pb)
+    return r
+
+
+def test_failed_launch_reports_device_error_and_stream_recovers(lk, ctx):
+    """A launch that fails on the host (its pyramid-table staging is made to
+    fail after the frame's copy was enqueued) completes its frame with
+    LK_ERR_DEVICE; the stream keeps its previous pyramid, so the next frame
+    is tracked from the last frame that completed."""
+    prm = lk.make_params(21, 3, 30, 0.01, 1e-6, 0.0)
+    cfg = lk.server_config(max_streams=2, max_points=200, levels=3, storage=0, params=prm, inflight=1)
+    w, h = 256, 192
+    frames = frames_for(7, w, h, 4)
+    pts = synth.uniform_points(np.random.default_rng(3), 120, w, h)
+    srv = lk.lk_server_create(ctx, cfg)
+    sid = lk.lk_server_open_stream(srv, w, h)
+    wait(lk, srv, lk.lk_server_submit(srv, sid, frames[0], pts), 200)          # primes
+    ok1 = wait(lk, srv, lk.lk_server_submit(srv, sid, frames[1], pts), 200)
+    lk.lk_server_fail_next_launches(srv, 1)
+    t2 = lk.lk_server_submit(srv, sid, frames[2], pts)
+    with pytest.raises(lk.LKError) as e:
+        wait(lk, srv, t2, 200)
+    assert e.value.code == lk.LK_ERR_DEVICE
+    with pytest.raises(lk.LKError) as e:
+        lk.lk_server_poll(srv, t2, 200)                                          # retired
+    assert e.value.code == lk.LK_ERR_NOT_FOUND
+    ok3 = wait(lk, srv, lk.lk_server_submit(srv, sid, frames[3], pts), 200)
+    st = lk.lk_server_get_stats(srv)
+    assert st.frames == 3                                                        # the failed frame is not counted
+    lk.lk_server_destroy(srv)
+    for got, (a, b) in ((ok1, (0, 1)), (ok3, (1, 3))):
+        ref = plain_track(lk, ctx, frames[a], frames[b], pts, prm, 3, 0)
+        for x, y in zip(got[:3], ref):
+            assert np.array_equal(x, y)
+
+
+def test_close_while_submitting(lk, ctx):
+    """Submits on a stream race with its close: every submit either gets a
+    ticket or a clean error, closing waits for copies in progress, and the
+    stream slot is reusable afterwards."""
+    import threading
+    prm = lk.make_params()
+    cfg = lk.server_config(max_streams=2, max_points=300, levels=3, storage=0, params=prm, queue_depth=4)
+    w, h = 640, 480
+    frames = frames_for(9, w, h, 3)
+    pts = synth.uniform_points(np.random.default_rng(4), 300, w, h)
+    srv = lk.lk_server_create(ctx, cfg)
+    for rnd in range(3):
+        sid = lk.lk_server_open_stream(srv, w, h)
+        codes, tickets = [], []
+        stop = threading.Event()
+
+        def submitter():
+            k = 0
+            while not stop.is_set():
+                try:
+                    tickets.append(lk.lk_server_submit(srv, sid, frames[k % 3], pts))
+                except lk.LKError as err:
+                    codes.append(err.code)
+                    if err.code == lk.LK_ERR_NOT_FOUND:
+                        return
+                k += 1
+        th = [threading.Thread(target=submitter) for _ in range(3)]
+        for t in th:
+            t.start()
+        time.sleep(0.02 * (rnd + 1))
+        lk.lk_server_close_stream(srv, sid)
+        stop.set()
+        for t in th:
+            t.join(timeout=30)
+            assert not t.is_alive()
+        assert set(codes) <= {lk.LK_ERR_BUSY, lk.LK_ERR_NOT_FOUND}
+        for t in tickets:                      # tickets of a closed stream are unknown or already done
+            try:
+                lk.lk_server_poll(srv, t, 300)
+            except lk.LKError as err:
+                assert err.code == lk.LK_ERR_NOT_FOUND
+    # the slot is free again and serves a stream of another size
+    sid = lk.lk_server_open_stream(srv, 320, 240)
+    f = frames_for(10, 320, 240, 2)
+    p2 = synth.uniform_points(np.random.default_rng(5), 100, 320, 240)
+    wait(lk, srv, lk.lk_server_submit(srv, sid, f[0], p2), 300)
+    r = wait(lk, srv, lk.lk_server_submit(srv, sid, f[1], p2), 300)
+    assert len(r[0]) == 100
+    assert lk.lk_server_get_stats(srv).open_streams == 1
+    lk.lk_server_destroy(srv)
+
+
+def test_served_c5_tracker_matches_oracle(lk, ctx):
+    """The serving configuration's tracker (31x31 window, 4 levels, 30
+    iterations, eps 0.01, forward-backward 1 px, binary16 storage) through
+    the server on four streams of different sizes, submitted interleaved:
+    every served frame follows the parity rule against the oracle with the
+    same binary16 storage, and stays within 1e-2 px of the unrounded FP64
+    oracle."""
+    import oracle
+    from parity import compare
+    prm = lk.make_params(31, 4, 30, 0.01, 1e-6, 1.0)
+    cfg = lk.server_config(max_streams=8, max_points=400, levels=4, storage=1, params=prm, inflight=2)
+    seqs = [synth.StereoSequence(21 + k, width=w, height=h, n_frames=8)
+            for k, (w, h) in enumerate([(752, 480), (640, 480), (960, 600), (400, 304)])]
+    kps = [200, 150, 300, 120]
+    frames = [[s.frame(t) for t in range(4)] for s in seqs]
+    srv = lk.lk_server_create(ctx, cfg)
+    sids = [lk.lk_server_open_stream(srv, s.width, s.height) for s in seqs]
+    served = [[None] * 4 for _ in seqs]
+    for t in range(4):
+        tk = [lk.lk_server_submit(srv, sid, frames[k][t], seqs[k].points(t, kps[k])) for k, sid in enumerate(sids)]
+        for k, ticket in enumerate(tk):
+            served[k][t] = wait(lk, srv, ticket, cfg.max_points)
+    stats = lk.lk_server_get_stats(srv)
+    lk.lk_server_destroy(srv)
+    assert stats.frames == 16 and stats.batches < 16
+    worst64, n_cmp = 0.0, 0
+    for k, s in enumerate(seqs):
+        for t in range(1, 4):
+            pts = s.points(t, kps[k])
+            g = served[k][t][:3]
+            r16 = oracle.track(frames[k][t - 1], frames[k][t], pts, win=31, levels=4, fb_thresh=1.0, min_eig=1e-6,
+                               f16=True, nthreads=8)
+            rep = compare(*g, None, r16, check_iters=False)
+            r64 = oracle.track(frames[k][t - 1], frames[k][t], pts, win=31, levels=4, fb_thresh=1.0, min_eig=1e-6,
+                               nthreads=8)
+            both = (g[1] == 0) & (r64.status == 0)
+            e64 = np.abs(g[0][both] - r64.pts[both]).max(axis=1)
+            print("stream %d frame %d: %s | vs FP64: %d points, max %.3g px" % (k, t, rep, both.sum(), e64.max()))
+            assert rep.compared_ok >= 0.8 * kps[k]
+            assert e64.max() <= 1e-2
+            worst64 = max(worst64, float(e64.max()))
+            n_cmp += rep.compared_ok
+    print("served C5 tracker: %d points compared, max %.3g px vs the unrounded oracle" % (n_cmp, worst64))
