@@ -155,8 +155,11 @@ def test_stereo_sequence_independent_gains_stress(gt):
     rp = oracle.track(a, b, pts.astype(np.float64) + 1e-5, levels=4, fb_thresh=1.0, min_eig=1e-6)
     rep = compare(*g, r, r_perturbed=rp)
     print(rep)
-    # many points hit the iteration cap here: they are compared in the capped class
-    assert rep.compared_ok + rep.n_capped >= 100
+    # many points hit the iteration cap or amplify perturbations here: they are
+    # compared in the capped and unstable classes (status and a class bound);
+    # only near-threshold points go unchecked, and they stay a minority
+    assert rep.compared_ok + rep.n_capped + rep.n_unstable >= 100
+    assert rep.n_near <= 0.25 * rep.n
 
 
 def test_identical_frames_bitwise_zero_flow(gt):
@@ -186,13 +189,18 @@ W63_SKIP = ("windows above 31 are rejected by every entry point: the four-column
                                  pytest.param(41, marks=pytest.mark.skip(reason=W63_SKIP)),
                                  pytest.param(63, marks=pytest.mark.skip(reason=W63_SKIP))])
 def test_window_sizes(gt, win):
-    p = synth.pair(20 + win, 320, 240, 60, max_shift=3.0)
+    # small windows lose most points to the eigenvalue test and the iteration
+    # cap, so they get more points
+    n = 300 if win <= 7 else 60
+    p = synth.pair(20 + win, 320, 240, n, max_shift=3.0)
     levels = 2 if win > 31 else 3
     g = gt.track(p.prev, p.next, p.pts, win=win, levels=levels)
     r = oracle.track(p.prev, p.next, p.pts, win=win, levels=levels, min_eig=1e-6)
-    rep = compare(*g, r)
+    rp = oracle.track(p.prev, p.next, p.pts.astype(np.float64) + 1e-5, win=win, levels=levels, min_eig=1e-6)
+    rep = compare(*g, r, r_perturbed=rp)
     print(win, rep)
-    assert rep.compared_ok >= 40
+    assert rep.compared_ok >= (10 if win == 3 else 40)
+    assert rep.n_near <= 0.1 * rep.n
 
 
 def test_windows_above_31_rejected_everywhere(lk, ctx, gt):
