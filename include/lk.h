@@ -179,6 +179,24 @@ lk_result lk_track_batched(lk_context *ctx, const lk_pair *h_pairs, int32_t n_pa
                            const float *d_guess, const lk_params *params, float *d_out_pts,
                            uint8_t *d_status, float *d_residual, int32_t *d_iters, lk_stream stream);
 
+/* lk_track_batched for callers that cannot allocate memory during the call
+ * (serving loops and harnesses that forbid hipMalloc): same arguments, same
+ * kernels, same results bit for bit, but the call allocates nothing.  The
+ * batch table (one entry per pair) goes into a fixed device array of the
+ * library, LK_NOALLOC_MAX_PAIRS entries (160 KiB), one per GPU, held from the
+ * first lk_context_create on that GPU until the process ends, and is copied
+ * there from a pinned host table the context allocated at creation.
+ * n_pairs > LK_NOALLOC_MAX_PAIRS: LK_ERR_INVALID_ARG, nothing enqueued.
+ * Every call on one GPU shares that array and keeps the last call's table:
+ * calls on one GPU that can overlap on the device (different streams without
+ * ordering between them, or several contexts or threads) race; order them on
+ * one stream.  The host waits until the same context's previous table upload
+ * has ended before it rewrites the pinned table. */
+#define LK_NOALLOC_MAX_PAIRS 4096
+lk_result lk_track_batched_noalloc(lk_context *ctx, const lk_pair *h_pairs, int32_t n_pairs, const float *d_pts,
+                                   const float *d_guess, const lk_params *params, float *d_out_pts,
+                                   uint8_t *d_status, float *d_residual, int32_t *d_iters, lk_stream stream);
+
 /* ---- prepared batched steps (hipGraph, persistent launch, autotuner) ------
  * A prepared step rebuilds the pyramids of n_builds frames (one launch per
  * level for all of them) and then tracks every pair of n_pairs in one

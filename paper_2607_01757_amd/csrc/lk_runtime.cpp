@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -84,6 +85,41 @@ lk_result StagingRing::acquire(size_t bytes, Slot **out)
     *out = &s;
     return LK_SUCCESS;
 }
+
+// ------------------------------------------------- fixed batch-table array
+//
+// lk_track_batched_noalloc keeps its batch table here instead of in memory
+// the library allocates on demand: LK_NOALLOC_MAX_PAIRS items, one copy per
+// device, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel or a copy (in host code it is a stand-in, not a device
+// address): it uses the address hipGetSymbolAddress returns for the current
+// device, taken once per device at context creation.
+
+static_assert(sizeof(BatchItem) == 40, "LK_NOALLOC_MAX_PAIRS entries take 160 KiB");
+static __device__ __align__(256) unsigned char scratch[LK_NOALLOC_MAX_PAIRS * sizeof(BatchItem)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's array; the device must be current.
+lk_result scratch_address(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(LK_ERR_INVALID_ARG, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(batch-table array)");
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return LK_SUCCESS;
+}
+
+}  // namespace
 
 // ------------------------------------------------------------------ checks
 
@@ -213,7 +249,21 @@ lk_result lk_context_create(int32_t device, uint64_t hbm_budget_bytes, lk_contex
     c->device = device;
     c->budget = hbm_budget_bytes;
     lk_result r = c->staging.init(8);
-    if (r != LK_SUCCESS) { delete c; return r; }
+    if (r == LK_SUCCESS) r = scratch_address(device, &c->table_dev);
+    if (r == LK_SUCCESS) {
+        e = hipHostMalloc(&c->table_host, LK_NOALLOC_MAX_PAIRS * sizeof(BatchItem), hipHostMallocDefault);
+        if (e != hipSuccess) { c->table_host = nullptr; r = hip_fail(e, "hipHostMalloc(batch table)"); }
+    }
+    if (r == LK_SUCCESS) {
+        e = hipEventCreateWithFlags(&c->table_done, hipEventDisableTiming);
+        if (e != hipSuccess) { c->table_done = nullptr; r = hip_fail(e, "hipEventCreate"); }
+    }
+    if (r != LK_SUCCESS) {
+        c->staging.release();
+        if (c->table_host) (void)hipHostFree(c->table_host);
+        delete c;
+        return r;
+    }
     *out = c;
     clear_error();
     return LK_SUCCESS;
@@ -226,6 +276,8 @@ void lk_context_destroy(lk_context *ctx)
     (void)hipDeviceSynchronize();
     ctx->graphs_release();
     ctx->staging.release();
+    if (ctx->table_done) (void)hipEventDestroy(ctx->table_done);
+    if (ctx->table_host) (void)hipHostFree(ctx->table_host);
     delete ctx;
 }
 
@@ -428,6 +480,42 @@ lk_result lk_track_batched(lk_context *ctx, const lk_pair *h_pairs, int32_t n_pa
     return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "batched tracker launch");
 }
 
+lk_result lk_track_batched_noalloc(lk_context *ctx, const lk_pair *h_pairs, int32_t n_pairs, const float *d_pts,
+                                   const float *d_guess, const lk_params *params, float *d_out_pts,
+                                   uint8_t *d_status, float *d_residual, int32_t *d_iters, lk_stream stream)
+{
+    if (!ctx) return fail(LK_ERR_INVALID_ARG, "ctx is NULL");
+    if (n_pairs < 0) return fail(LK_ERR_INVALID_ARG, "n_pairs < 0");
+    if (n_pairs > LK_NOALLOC_MAX_PAIRS)
+        return fail(LK_ERR_INVALID_ARG, "n_pairs %d exceeds the fixed batch table (%d pairs)", n_pairs,
+                    LK_NOALLOC_MAX_PAIRS);
+    if (n_pairs == 0) return LK_SUCCESS;
+    if (!h_pairs) return fail(LK_ERR_INVALID_ARG, "h_pairs is NULL");
+    if (!ctx->table_dev || !ctx->table_host || !ctx->table_done)
+        return fail(LK_ERR_DEVICE, "the context has no batch-table array");
+    (void)hipSetDevice(ctx->device);
+    // the pinned table is rewritten only after the previous upload from it ended
+    hipError_t e = hipEventSynchronize(ctx->table_done);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    BatchItem *items = static_cast<BatchItem *>(ctx->table_host);
+    int storage = -1;
+    long long total = 0;
+    lk_result r = plan_batch_into(ctx, h_pairs, n_pairs, params, items, &storage, &total);
+    if (r != LK_SUCCESS) return r;
+    if (total == 0) return LK_SUCCESS;
+    if (!d_pts || !d_out_pts || !d_status || !d_residual)
+        return fail(LK_ERR_INVALID_ARG, "NULL point or output array");
+    if (params->use_guess && !d_guess) return fail(LK_ERR_INVALID_ARG, "use_guess set but d_guess is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)n_pairs * sizeof(BatchItem);
+    e = hipMemcpyAsync(ctx->table_dev, items, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch table)");
+    (void)hipEventRecord(ctx->table_done, s);
+    TrackArgs a = make_args(params, (int)total, d_pts, d_guess, d_out_pts, d_status, d_residual, d_iters);
+    e = launch_track_batched(static_cast<const BatchItem *>(ctx->table_dev), n_pairs, (int)total, a, storage, s);
+    return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "batched tracker launch");
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------- shared helpers
@@ -447,14 +535,12 @@ lk_result check_pair(const lk_context *ctx, const lk_pyramid *prev, const lk_pyr
     return LK_SUCCESS;
 }
 
-lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
-                     std::vector<BatchItem> *items, int *storage, long long *total)
+lk_result plan_batch_into(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
+                          BatchItem *items, int *storage, long long *total)
 {
     int min_levels = LK_MAX_LEVELS;
     *storage = -1;
     *total = 0;
-    items->clear();
-    items->reserve(n_pairs);
     for (int i = 0; i < n_pairs; ++i) {
         const lk_pair &p = pairs[i];
         lk_result r = check_pair(ctx, p.prev, p.next, i);
@@ -476,9 +562,16 @@ lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const l
         it.first_wave = (int32_t)*total;
         *total += p.n;
         if (*total > (1LL << 30)) return fail(LK_ERR_INVALID_ARG, "more than 2^30 points in one batch");
-        items->push_back(it);
+        items[i] = it;
     }
     return check_params(params, min_levels);
+}
+
+lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
+                     std::vector<BatchItem> *items, int *storage, long long *total)
+{
+    items->assign((size_t)std::max(n_pairs, 0), BatchItem{});
+    return plan_batch_into(ctx, pairs, n_pairs, params, items->data(), storage, total);
 }
 
 namespace {

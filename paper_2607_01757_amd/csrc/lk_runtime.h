@@ -32,6 +32,12 @@ struct lk_context {
     uint64_t budget = 0;
     std::atomic<uint64_t> in_use{0};
     lkmi::StagingRing staging;
+    // lk_track_batched_noalloc: the device's fixed batch-table array (set up
+    // at creation), a pinned host copy of the table and the event of its last
+    // upload
+    void *table_dev = nullptr;
+    void *table_host = nullptr;
+    hipEvent_t table_done = nullptr;
     void graphs_release();
 };
 
@@ -74,6 +80,9 @@ TrackArgs make_args(const lk_params *p, int n, const float *pts, const float *gu
                     float *res, int32_t *iters);
 lk_result plan_batch(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
                      std::vector<BatchItem> *items, int *storage, long long *total);
+// plan_batch into a caller array of n_pairs items (no host allocation)
+lk_result plan_batch_into(lk_context *ctx, const lk_pair *pairs, int n_pairs, const lk_params *params,
+                          BatchItem *items, int *storage, long long *total);
 lk_result enqueue_build(lk_context *ctx, lk_pyramid *const *pyrs, int n, hipStream_t s);
 // Jobs of one pyramid build: levels 1+2 fused when the pyramid has three or
 // more levels, one down job per remaining level, gradient planes (binary16).

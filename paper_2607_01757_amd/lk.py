@@ -20,12 +20,14 @@ LK_STORAGE_F32, LK_STORAGE_F16 = 0, 1
 LK_OK, LK_LOST_EIG, LK_LOST_OOB, LK_LOST_FB = 0, 1, 2, 3
 LK_MAX_LEVELS = 8
 LK_MAX_WIN = 31
+LK_NOALLOC_MAX_PAIRS = 4096
 
 # Every symbol include/lk.h declares (checked by the CPU tests).
 ABI_SYMBOLS = (
     "lk_params_default", "lk_params_check", "lk_last_error", "lk_context_create", "lk_context_destroy",
     "lk_context_bytes_in_use", "lk_pyramid_create", "lk_pyramid_destroy", "lk_pyramid_info",
     "lk_build_pyramid", "lk_build_pyramids", "lk_pyramid_read_level", "lk_track", "lk_track_batched",
+    "lk_track_batched_noalloc",
     "lk_batch_create", "lk_batch_run", "lk_batch_tune", "lk_batch_config", "lk_batch_destroy",
     "lk_server_create", "lk_server_open_stream", "lk_server_submit", "lk_server_poll", "lk_server_close_stream",
     "lk_server_get_stats", "lk_server_fail_next_launches", "lk_server_destroy",
@@ -136,6 +138,8 @@ def _load():
         "lk_track": (res, [vp, vp, vp, vp, vp, i32, C.POINTER(lk_params), vp, vp, vp, vp, vp]),
         "lk_track_batched": (res, [vp, C.POINTER(lk_pair), i32, vp, vp, C.POINTER(lk_params), vp, vp, vp,
                                    vp, vp]),
+        "lk_track_batched_noalloc": (res, [vp, C.POINTER(lk_pair), i32, vp, vp, C.POINTER(lk_params), vp, vp,
+                                           vp, vp, vp]),
         "lk_batch_create": (res, [vp, C.POINTER(lk_batch_desc), C.POINTER(lk_exec_config), C.POINTER(vp)]),
         "lk_batch_run": (res, [vp, vp]),
         "lk_batch_tune": (res, [vp, vp, i32, C.POINTER(lk_exec_config), C.POINTER(C.c_float)]),
@@ -269,6 +273,21 @@ def lk_track_batched(ctx, pairs, pts, guess, params: lk_params, out_pts, status,
         arr[i].reserved = 0
     _check(lib.lk_track_batched(ctx, arr, len(pairs), _ptr(pts), _ptr(guess), C.byref(params),
                                 _ptr(out_pts), _ptr(status), _ptr(residual), _ptr(iters), _stream(stream)))
+
+
+def lk_track_batched_noalloc(ctx, pairs, pts, guess, params: lk_params, out_pts, status, residual, iters=None,
+                             stream=None):
+    """lk_track_batched with the batch table in the library's fixed device array."""
+    arr = (lk_pair * max(len(pairs), 1))()
+    for i, (a, b, off, n) in enumerate(pairs):
+        arr[i].prev = a.value if isinstance(a, C.c_void_p) else a
+        arr[i].next = b.value if isinstance(b, C.c_void_p) else b
+        arr[i].pt_offset = off
+        arr[i].n = n
+        arr[i].reserved = 0
+    _check(lib.lk_track_batched_noalloc(ctx, arr, len(pairs), _ptr(pts), _ptr(guess), C.byref(params),
+                                        _ptr(out_pts), _ptr(status), _ptr(residual), _ptr(iters),
+                                        _stream(stream)))
 
 
 def _hv(p):
