@@ -212,19 +212,40 @@ def profiled_traffic(kernel, summary="profiles/hbm_counters_batched64.txt",
     return None
 
 
-def cpu_baseline(streams, n_sample, win, levels, fb):
+def cpu_baseline(streams, n_sample, win, levels, fb, n_sample_1t=6):
+    """The FP64 oracle timed on the host: on every core over n_sample streams,
+    and on one thread over the first n_sample_1t of them."""
     import oracle
     threads = os.cpu_count() or 1
-    sample = streams[:n_sample]
-    npts = sum(len(s.pts) for s in sample)
-    t0 = time.perf_counter()
-    for s in sample:
-        oracle.track(s.prev, s.next, s.pts, win=win, levels=levels, min_eig=1e-6, fb_thresh=fb, nthreads=threads)
-    dt = time.perf_counter() - t0
+
+    def timed(sample, nthreads):
+        npts = sum(len(s.pts) for s in sample)
+        t0 = time.perf_counter()
+        for s in sample:
+            oracle.track(s.prev, s.next, s.pts, win=win, levels=levels, min_eig=1e-6, fb_thresh=fb,
+                         nthreads=nthreads)
+        return npts, time.perf_counter() - t0
+
+    npts, dt = timed(streams[:n_sample], threads)
+    n1, dt1 = timed(streams[:n_sample_1t], 1)
     return {"value": npts / dt, "unit": "keypoints/s", "cores": threads, "kind": "oracle",
             "sample": "%d of %d streams, all %d of their keypoints; the oracle builds both pyramids of "
                       "each pair (FP64) and tracks on %d threads; %.1f s wall" % (n_sample, len(streams), npts,
-                                                                                  threads, dt)}
+                                                                                  threads, dt),
+            "one_thread": {"value": n1 / dt1, "unit": "keypoints/s", "cores": 1,
+                           "sample": "the first %d streams, %d keypoints, %.1f s wall" % (n_sample_1t, n1, dt1)}}
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=20):
+    """Attainable HBM bandwidth: a device-to-device copy of nbytes, timed
+    with HIP events over reps back-to-back copies (read + write bytes)."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    t = time_block(lambda: b.copy_(a), reps, 3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / t / 1e9
 
 
 def run_batched(args):
@@ -312,6 +333,8 @@ def run_batched(args):
     b_io = wl.n * (8 + 8 + 1 + 4)
     b_alg = b_frames + b_levels + b_windows + b_io
     step_s = wall / args.steps
+    copy_gbs = copy_bandwidth()
+    log("device copy: %.0f GB/s (read + write)" % copy_gbs)
 
     result = {
         "metric": "tracked keypoints/sec (batched, 64 streams) + p50/p99 frame latency",
@@ -334,7 +357,8 @@ def run_batched(args):
                      "traffic": None if f16 else profiled_traffic("k_track_batched"),
                      "flops_per_launch": f_alg, "kernel_ms": t_trk * 1e3},
         "path_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": b_alg / step_s / 1e9,
-                     "frac": b_alg / step_s / 1e9 / PEAK_HBM_GBS},
+                     "frac": b_alg / step_s / 1e9 / PEAK_HBM_GBS,
+                     "copy_GBs": copy_gbs, "frac_of_copy": b_alg / step_s / 1e9 / copy_gbs},
         "pyramid_ms": t_pyr * 1e3,
         "unprepared_batched": unprepared,
         "plain": plain,
@@ -349,12 +373,66 @@ def run_batched(args):
     return result
 
 
+_SEQ = None
+
+
+def _render_init(seed, nf, gain_mode):
+    global _SEQ
+    import synth
+    _SEQ = synth.StereoSequence(seed, n_frames=nf, gain_mode=gain_mode)
+
+
+def _render_frame(t):
+    return _SEQ.frame(t, 0), _SEQ.frame(t, 1)
+
+
+def render_stereo(seed, nf, gain_mode):
+    """Both cameras of frames 0 .. nf-1, rendered by a pool of host processes
+    (forked before this process touches the GPU)."""
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    if workers == 1 or nf < 32:
+        _render_init(seed, nf, gain_mode)
+        frames = [_render_frame(t) for t in range(nf)]
+    else:
+        with mp.get_context("fork").Pool(workers, initializer=_render_init, initargs=(seed, nf, gain_mode)) as pool:
+            frames = pool.map(_render_frame, range(nf), chunksize=8)
+    return [f[0] for f in frames], [f[1] for f in frames]
+
+
+def _pass_error(records, frames_a, frames_b, win, levels, label):
+    """Every recorded tracker call of one pass against the FP64 oracle
+    (unrounded pyramids): end-point error over points both track, and status
+    agreement over all points."""
+    import oracle
+    errs, agree, total, both = [], 0, 0, 0
+    t0 = time.time()
+    for k, (t, p0, g_pts, g_st) in enumerate(records):
+        r = oracle.track(frames_a(t), frames_b(t), p0, win=win, levels=levels, fb_thresh=1.0, min_eig=1e-6,
+                         nthreads=os.cpu_count() or 1)
+        ok = (g_st == 0) & (r.status == 0)
+        errs.append(np.abs(g_pts[ok] - r.pts[ok]).max(axis=1))
+        agree += int(np.sum(g_st == r.status))
+        total += len(g_st)
+        both += int(ok.sum())
+        if (k + 1) % 200 == 0:
+            log("  %s pass: %d / %d frames against the oracle (%.0f s)" % (label, k + 1, len(records),
+                                                                          time.time() - t0))
+    e = np.concatenate(errs) if errs else np.zeros(0)
+    return {"frames": len(records), "points": total, "tracked_by_both": both,
+            "max_px": float(e.max()) if e.size else 0.0, "p99_px": float(np.percentile(e, 99)) if e.size else 0.0,
+            "over_1e-3_px": int(np.sum(e > 1e-3)), "over_1e-2_px": int(np.sum(e > 1e-2)),
+            "status_agreement": agree / total if total else 1.0, "status_differs": total - agree}
+
+
 def run_stereo(args, f16):
     """Stereo sequence: per frame, pyramids of the left and right frames,
     temporal tracking (left t-1 -> t) and stereo tracking (left -> right),
     both with a 1 px forward-backward check; 200 keypoints per frame
     (survivors carried, topped up with new points).  Plain per-frame
-    launches, and the same two pairs as one batch of two."""
+    launches, and the same two pairs as one batch of two.  Every tracker
+    call of the timed run is then compared with the FP64 oracle (both
+    passes, every frame)."""
     import torch
     import synth
     from paper_2607_01757_amd import lk
@@ -362,10 +440,9 @@ def run_stereo(args, f16):
     win, levels = (31, 4) if f16 else (21, 4)
     storage = lk.LK_STORAGE_F16 if f16 else lk.LK_STORAGE_F32
     nf = args.frames
-    seq = synth.StereoSequence(args.seed, n_frames=max(nf, 2))
+    seq = synth.StereoSequence(args.seed, n_frames=max(nf, 2), gain_mode=args.gain_mode)
     t_r = time.time()
-    left = [seq.frame(t, 0) for t in range(nf)]
-    right = [seq.frame(t, 1) for t in range(nf)]
+    left, right = render_stereo(args.seed, max(nf, 2), args.gain_mode)
     log("rendered %d stereo frames in %.1fs" % (nf, time.time() - t_r))
     ctx = lk.lk_context_create(0, 0)
     W, H = seq.width, seq.height
@@ -377,85 +454,76 @@ def run_stereo(args, f16):
     N = 200
     outs = [lk.outputs(N, levels) for _ in range(2)]
     d_pts = torch.empty((2 * N, 2), dtype=torch.float32, device="cuda")
-    out_all = lk.outputs(2 * N, levels)
 
     def run(mode, record):
         rng = np.random.default_rng(args.seed)
         pts = synth.uniform_points(rng, N, W, H)
         lk.lk_build_pyramid(ctx, pl[0], dl[0])
         torch.cuda.synchronize()
-        lat, kp, inputs = [], 0, []
+        lat, kp, temporal, stereo = [], 0, [], []
         t0 = time.perf_counter()
         for t in range(1, nf):
             a, b = pl[(t - 1) & 1], pl[t & 1]
             ts = time.perf_counter()
+            p_in = pts
             d_pts[:N].copy_(torch.from_numpy(pts))
             if mode == "plain":
                 lk.lk_build_pyramid(ctx, b, dl[t])
                 lk.lk_build_pyramid(ctx, pr, dr[t])
-                lk.lk_track(ctx, a, b, d_pts[:N], None, N, prm, *outs[0][:3], None)
-                st = outs[0][1].cpu().numpy()
-                q = outs[0][0].cpu().numpy()
             else:
                 lk.lk_build_pyramids(ctx, [b, pr], [dl[t], dr[t]])
-                lk.lk_track(ctx, a, b, d_pts[:N], None, N, prm, *outs[0][:3], None)
-                st = outs[0][1].cpu().numpy()
-                q = outs[0][0].cpu().numpy()
+            lk.lk_track(ctx, a, b, d_pts[:N], None, N, prm, *outs[0][:3], None)
+            st = outs[0][1].cpu().numpy()
+            q = outs[0][0].cpu().numpy()
             if record:
-                inputs.append((t, pts.copy()))
+                temporal.append((t, p_in.copy(), q.astype(np.float64), st.copy()))
             keep = q[st == 0]
             keep = keep[(keep[:, 0] >= 16) & (keep[:, 0] <= W - 17) & (keep[:, 1] >= 16) & (keep[:, 1] <= H - 17)]
             new = synth.uniform_points(rng, N - len(keep), W, H)
             pts = np.concatenate([keep, new]).astype(np.float32)[:N]
             d_pts[N:].copy_(torch.from_numpy(pts))
             lk.lk_track(ctx, b, pr, d_pts[N:], None, N, prm, *outs[1][:3], None)
-            _ = outs[1][1].cpu().numpy()
+            st2 = outs[1][1].cpu().numpy()
+            if record:
+                stereo.append((t, pts.copy(), outs[1][0].cpu().numpy().astype(np.float64), st2.copy()))
             lat.append((time.perf_counter() - ts) * 1e3)
             kp += 2 * N
         wall = time.perf_counter() - t0
-        return kp / wall, lat, inputs
+        return kp / wall, lat, temporal, stereo
 
     run("plain", False)                                   # warm-up
-    kps, lat, inputs = run("plain", True)
-    kps_b, lat_b, _ = run("batch2", False)
-    log("stereo %s: plain %.3g kp/s p50 %.3f ms p99 %.3f ms; left+right pyramids in one launch %.3g kp/s p99 %.3f ms" % (
-        "f16" if f16 else "f32", kps, percentile(lat, 50), percentile(lat, 99), kps_b, percentile(lat_b, 99)))
+    kps, lat, temporal, stereo = run("plain", True)
+    kps_b, lat_b, _, _ = run("batch2", False)
+    log("stereo %s (%s gains): plain %.3g kp/s p50 %.3f ms p99 %.3f ms; left+right pyramids in one launch %.3g kp/s "
+        "p99 %.3f ms" % ("f16" if f16 else "f32", args.gain_mode, kps, percentile(lat, 50), percentile(lat, 99),
+                         kps_b, percentile(lat_b, 99)))
     result = {
         "metric": "tracked keypoints/sec + p50/p99 frame latency (stereo sequence, plain per-frame)",
         "value": kps, "unit": "keypoints/s", "n_gpus": 1, "steps": nf - 1, "warmup": nf - 1,
         "ms_per_step": float(np.mean(lat)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f16" if f16 else "f32", "data": "synthetic",
-        "config": {"workload": "stereo sequence 752x480, %d frames, 200 keypoints, temporal + left-to-right with "
-                               "FB 1 px, %dx%d, 4 levels, %s storage" % (nf, win, win, "binary16" if f16 else "float32")},
+        "config": {"workload": "stereo sequence 752x480, %d frames, %s gains, 200 keypoints, temporal + "
+                               "left-to-right with FB 1 px, %dx%d, 4 levels, %s storage" % (
+                                   nf, args.gain_mode, win, win, "binary16" if f16 else "float32")},
         "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
         "batch2": {"value": kps_b, "p50_frame_ms": percentile(lat_b, 50), "p99_frame_ms": percentile(lat_b, 99)},
     }
-    if True:
-        # error of the temporal pass of a few frames vs the FP64 oracle
-        # (without storage rounding)
-        import oracle
-        errs = []
-        for (t, p0) in inputs[:args.precision_frames]:
-            pa = lk.lk_pyramid_create(ctx, W, H, levels, storage)
-            pb = lk.lk_pyramid_create(ctx, W, H, levels, storage)
-            lk.lk_build_pyramid(ctx, pa, dl[t - 1])
-            lk.lk_build_pyramid(ctx, pb, dl[t])
-            d_pts[:N].copy_(torch.from_numpy(p0))
-            lk.lk_track(ctx, pa, pb, d_pts[:N], None, N, prm, *outs[0][:3], None)
-            g_pts, g_st = outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()
-            r = oracle.track(left[t - 1], left[t], p0, win=win, levels=levels, fb_thresh=1.0, min_eig=1e-6,
-                             nthreads=os.cpu_count() or 1)
-            ok = (g_st == 0) & (r.status == 0)
-            errs.extend(np.abs(g_pts[ok] - r.pts[ok]).max(axis=1).tolist())
-            lk.lk_pyramid_destroy(pa)
-            lk.lk_pyramid_destroy(pb)
-        result["error_vs_fp64_oracle_px"] = {"max": float(np.max(errs)), "p99": float(np.percentile(errs, 99)),
-                                             "points": len(errs), "frames": args.precision_frames}
-        log("%s storage vs FP64 oracle: max %.3g px p99 %.3g px over %d points" % (
-            "binary16" if f16 else "float32", np.max(errs), np.percentile(errs, 99), len(errs)))
     for p_ in pl + [pr]:
         lk.lk_pyramid_destroy(p_)
     lk.lk_context_destroy(ctx)
+    if args.precision_frames != 0:
+        nrec = len(temporal) if args.precision_frames < 0 else min(args.precision_frames, len(temporal))
+        log("comparing %d frames of both passes with the FP64 oracle (unrounded pyramids) ..." % nrec)
+        err = {
+            "temporal": _pass_error(temporal[:nrec], lambda t: left[t - 1], lambda t: left[t], win, levels,
+                                    "temporal"),
+            "stereo": _pass_error(stereo[:nrec], lambda t: left[t], lambda t: right[t], win, levels, "stereo"),
+        }
+        result["error_vs_fp64_oracle_px"] = err
+        for k, v in err.items():
+            log("%s storage, %s pass vs FP64 oracle: max %.3g px p99 %.3g px over %d points tracked by both; "
+                "status agrees on %.4f of %d" % ("binary16" if f16 else "float32", k, v["max_px"], v["p99_px"],
+                                                   v["tracked_by_both"], v["status_agreement"], v["points"]))
     return result
 
 
@@ -1067,8 +1135,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "pair", "stereo", "stereo16", "serve",
                                                            "detect", "sweep", "frontend", "epipolar", "copy"])
-    ap.add_argument("--frames", type=int, default=100)
-    ap.add_argument("--precision-frames", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=1000, help="stereo workloads: sequence length")
+    ap.add_argument("--precision-frames", type=int, default=-1,
+                    help="stereo workloads: frames compared with the FP64 oracle (-1: all, 0: none)")
+    ap.add_argument("--gain-mode", choices=["smooth", "iid"], default="smooth",
+                    help="stereo workloads: exposure drifting smoothly in [0.9, 1.1], or drawn per frame")
     ap.add_argument("--serve-streams", type=int, default=256)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
