@@ -655,6 +655,21 @@ __device__ __forceinline__ float2 bload_h2(const __amdgpu_buffer_rsrc_t &rs, int
     return __half22float2(__builtin_bit_cast(__half2, __builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4, 0, 0)));
 }
 
+// Taps x and x+1 of one row of an 8-bit or binary16 plane (boff: byte offset
+// of x) with one 8-byte load from the 4-byte-aligned offset at or below it,
+// which holds both: one memory instruction instead of two.  The caller keeps
+// the 8 bytes inside the plane (the bytes past x+1 are read and dropped).
+template <int KIND>
+__device__ __forceinline__ float2 bload_pair(const Plane &p, int boff, int soff)
+{
+    static_assert(KIND == K_U8 || KIND == K_F16, "8-bit or binary16 elements");
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(p.rs, boff & ~3, soff, 0);
+    const uint32_t lo = v[0], hi = v[1];    // (copied out: see fast_template_planes)
+    const uint32_t w = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(boff & 3) * 8u);
+    if constexpr (KIND == K_U8) return make_float2((float)(w & 0xFFu), (float)((w >> 8) & 0xFFu));
+    else return __half22float2(__builtin_bit_cast(__half2, w));
+}
+
 // LDS writes of a wavefront become visible to its other lanes.
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -911,12 +926,31 @@ __device__ __forceinline__ void lane_template(const float *lds, const LaneCfg &l
 // indices clamped to the level (bilinear taps replicate the edges).
 // `inside`: the taps of every lane lie inside the level (decided for the
 // whole wavefront by the caller), so no index needs clamping.
-template <class G, int KIND>
+template <class G, int KIND, bool PAIR = false>
 __device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, bool inside,
                                           float (&t)[G::R + 1][G::CW + 1])
 {
     if (inside) {
-        if constexpr (G::R <= 7) {
+        if constexpr (PAIR) {
+            // one 8-byte load per row (bload_pair; the caller keeps the taps
+            // off the level's last row); scalar row offsets only while they
+            // keep the loads 4-byte aligned
+            static_assert(G::CW == 1, "one window column per lane");
+            constexpr int es = KIND == K_U8 ? 1 : 2;
+            const int voff = (by * P.pitch + bx) * es;
+            auto rows = [&](auto scalar_rows) {
+                constexpr bool SR = decltype(scalar_rows)::value;
+#pragma unroll
+                for (int i = 0; i <= G::R; ++i) {
+                    const float2 ab = bload_pair<KIND>(P, SR ? voff : voff + i * P.pitch * es,
+                                                       SR ? i * P.pitch * es : 0);
+                    t[i][0] = ab.x;
+                    t[i][1] = ab.y;
+                }
+            };
+            if (G::R <= 7 && ((P.pitch * es) & 3) == 0) rows(std::true_type{});
+            else rows(std::false_type{});
+        } else if constexpr (G::R <= 7) {
             // one vector offset for the lane's first tap; the row offsets are
             // wave-uniform and go in the scalar offset of each load (taller
             // strips keep per-row vector offsets: their scalar registers are
@@ -949,11 +983,11 @@ __device__ __forceinline__ void load_taps(const Plane &P, int bx, int by, bool i
 
 // Target taps of a lane (load_taps); the one-column layouts keep each tap
 // row as (left, right - left) for lerp_row.
-template <class G, int KIND>
+template <class G, int KIND, bool PAIR = false>
 __device__ __forceinline__ void load_lane_taps(const Plane &P, int bx, int by, bool inside,
                                                float (&t)[G::R + 1][G::CW + 1])
 {
-    load_taps<G, KIND>(P, bx, by, inside, t);
+    load_taps<G, KIND, PAIR>(P, bx, by, inside, t);
     if constexpr (G::CW == 1)
 #pragma unroll
         for (int i = 0; i <= G::R; ++i) t[i][1] = t[i][1] - t[i][0];
@@ -1111,6 +1145,70 @@ __device__ __forceinline__ void fast_template(const Plane &P, int tx_lo, int ty_
         strip(Tb + lc.r0 * TBS + lc.c0, std::true_type{});
 }
 
+// Template of a window whose taps lie inside the level, binary16 storage
+// (one column per lane): each lane loads the taps of its strip straight into
+// registers -- R+1 rows of left and right taps of the stored level (8-bit at
+// level 0) and of the stored (Gx, Gy) plane, one 8-byte load per row of each
+// -- and samples T, Gx and Gy in the lerp form the target samples use.
+// No LDS.  (bx, by): the lane's first tap; the caller keeps the taps off the
+// level's last row (the level's 8-byte loads read up to 3 elements past the
+// right tap, which stays inside the level's buffer on every other row).  An
+// idle lane of an exact build reads beyond the buffers (zeros), so its T,
+// Gx and Gy are zero.
+template <class G, int KIND>
+__device__ __forceinline__ void fast_template_planes(const Plane &P, const LevelDesc &L, int bx, int by, float ax,
+                                                     float ay, const LaneCfg &lc, int win, float (&T)[G::R][G::CW],
+                                                     float (&GX)[G::R][G::CW], float (&GY)[G::R][G::CW])
+{
+    static_assert(G::CW == 1, "one window column per lane");
+    constexpr int R = G::R;
+    constexpr int es = KIND == K_U8 ? 1 : 2;
+    constexpr int kFar = 0x40000000;       // beyond every level and gradient plane
+    const __amdgpu_buffer_rsrc_t grs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<__half2 *>(L.grad), (short)0, L.gpitch * L.h * 4, kBufWord3);
+    const bool live = !G::EXACT || lc.active;
+    const int voff = live ? (by * P.pitch + bx) * es : kFar;
+    const int goff = live ? (by * L.gpitch + bx) * 4 : kFar;
+    float el[R + 1], ed[R + 1], xl[R + 1], xd[R + 1], yl[R + 1], yd[R + 1];
+    // row offsets in scalar registers for short strips whose row pitch keeps
+    // the 8-byte loads aligned; otherwise in the vector offset (taller strips:
+    // their scalar registers are short)
+    auto rows = [&](auto scalar_rows) {
+        constexpr bool SR = decltype(scalar_rows)::value;
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+            const int vi = SR ? voff : voff + i * P.pitch * es;
+            const int si = SR ? i * P.pitch * es : 0;
+            const int gvi = SR ? goff : goff + i * L.gpitch * 4;
+            const int gsi = SR ? i * L.gpitch * 4 : 0;
+            const float2 ab = bload_pair<KIND>(P, vi, si);
+            const auto g = __builtin_amdgcn_raw_buffer_load_b64(grs, gvi, gsi, 0);
+            // elements copied to scalars first: a bit cast of a vector element
+            // itself reads element 0 whatever the index (clang codegen)
+            const uint32_t g0 = g[0], g1 = g[1];
+            const float2 gl = __half22float2(__builtin_bit_cast(__half2, g0));
+            const float2 gr = __half22float2(__builtin_bit_cast(__half2, g1));
+            el[i] = ab.x; ed[i] = ab.y - ab.x;
+            xl[i] = gl.x; xd[i] = gr.x - gl.x;
+            yl[i] = gl.y; yd[i] = gr.y - gl.y;
+        }
+    };
+    if (R <= 7 && ((P.pitch * es) & 3) == 0) rows(std::true_type{});
+    else rows(std::false_type{});
+    float e0 = lerp_row(ax, el[0], ed[0]), x0 = lerp_row(ax, xl[0], xd[0]), y0 = lerp_row(ax, yl[0], yd[0]);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const float e1 = lerp_row(ax, el[i + 1], ed[i + 1]);
+        const float x1 = lerp_row(ax, xl[i + 1], xd[i + 1]);
+        const float y1 = lerp_row(ax, yl[i + 1], yd[i + 1]);
+        const bool ok = g_valid<G>(lc, win, i, 0);
+        T[i][0] = lerp_col(ay, e0, e1);      // invalid pixels have GX = GY = 0: they add nothing
+        GX[i][0] = ok ? lerp_col(ay, x0, x1) : 0.0f;
+        GY[i][0] = ok ? lerp_col(ay, y0, y1) : 0.0f;
+        e0 = e1; x0 = x1; y0 = y1;
+    }
+}
+
 struct PassResult {
     int status;
     float ox, oy;      // end point, level-0 pixels
@@ -1191,7 +1289,21 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
             bool fast = false;
             if constexpr (ST == LK_STORAGE_F32 && G::CW == 1)
                 fast = tx_lo >= 0 && ty_lo >= 0 && tx_lo + G::SW <= LI.w && ty_lo + G::SH <= LI.h;
+            if constexpr (ST == LK_STORAGE_F16 && G::CW == 1) {
+                // every lane's taps (columns cix - h .. cix - h + EXX, rows
+                // likewise) inside the level
+                fast = cix - h >= 0 && ciy - h >= 0 && cix - h + G::EXX < LI.w && ciy - h + G::EXY < LI.h - 1;
+            }
             if (fast) {
+                if constexpr (ST == LK_STORAGE_F16 && G::CW == 1) {
+                    const int bx = cix - h + lc.c0, by = ciy - h + lc.r0;
+                    if (l == 0)
+                        fast_template_planes<G, K_U8>(make_plane<K_U8>(LI.img, LI.pitch, LI.w, LI.h), LI, bx, by, cfx,
+                                                      cfy, lc, win, T, GX, GY);
+                    else
+                        fast_template_planes<G, K_F16>(make_plane<K_F16>(LI.img, LI.pitch, LI.w, LI.h), LI, bx, by,
+                                                       cfx, cfy, lc, win, T, GX, GY);
+                }
                 if constexpr (ST == LK_STORAGE_F32 && G::CW == 1) {
                     if (l == 0)
                         fast_template<G, K_U8>(make_plane<K_U8>(LI.img, LI.pitch, LI.w, LI.h), tx_lo, ty_lo, cfx, cfy,
@@ -1247,11 +1359,16 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
                                                         : make_plane<K_F32>(LJ.img, LJ.pitch, LJ.w, LJ.h));
         // target taps of this level, whose first tap sits at (bx - h, by - h)
         float jt[R + 1][CW + 1];
+        // binary16 kernels load a row's two taps with one 8-byte load (memory
+        // instructions, not arithmetic, bound them), which must not start on
+        // the level's last row
+        constexpr bool PAIR = ST == LK_STORAGE_F16 && G::CW == 1;
         auto load_target = [&](int bx, int by) {
-            const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w && by - h + G::EXY < PJ.h;
-            if (l == 0) load_lane_taps<G, K_U8>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+            const bool inside = bx - h >= 0 && by - h >= 0 && bx - h + G::EXX < PJ.w &&
+                                by - h + G::EXY < PJ.h - (PAIR ? 1 : 0);
+            if (l == 0) load_lane_taps<G, K_U8, PAIR>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
             else if constexpr (ST == LK_STORAGE_F16)
-                load_lane_taps<G, K_F16>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
+                load_lane_taps<G, K_F16, PAIR>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
             else load_lane_taps<G, K_F32>(PJ, bx - h + lc.c0, by - h + lc.r0, inside, jt);
         };
         // The taps of the first estimate are loaded before the iterations

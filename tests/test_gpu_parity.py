@@ -327,3 +327,42 @@ def test_f16_storage_matches_f16_oracle(gt, t):
     print("f16 vs fp64-oracle: %d points, max %.4g p99 %.4g" % (both.sum(), err.max(), np.percentile(err, 99)))
     assert both.sum() >= 100
     assert err.max() <= 1e-2
+
+
+@pytest.mark.parametrize("win,w,h,pad", [(21, 333, 251, 0), (21, 333, 251, 7), (31, 97, 131, 5), (21, 640, 480, 0)])
+def test_f16_storage_odd_pitch_and_edges(lk, ctx, win, w, h, pad):
+    """binary16 storage with frames whose row pitch is odd or padded (8-bit
+    level 0 read in place), points over the whole frame with many within a
+    window of the bottom and right edges: the register-tap template and the
+    paired tap loads (one 8-byte load per row, kept off a level's last row)
+    against the binary16 oracle."""
+    import torch
+    p = synth.pair(60 + win + pad, w, h, 1)
+    rng = np.random.default_rng(win * 100 + pad)
+    pts = np.concatenate([rng.uniform([0, 0], [w - 1, h - 1], size=(250, 2)),
+                          rng.uniform([0, h - 20], [w - 1, h - 1], size=(100, 2)),
+                          rng.uniform([w - 20, 0], [w - 1, h - 1], size=(50, 2))]).astype(np.float32)
+    levels = 3
+    pyrs, bufs = [], []
+    for img in (p.prev, p.next):
+        buf = torch.zeros((h, w + pad), dtype=torch.uint8, device="cuda")
+        buf[:, :w] = torch.from_numpy(img).cuda()
+        pyr = lk.lk_pyramid_create(ctx, w, h, levels, lk.LK_STORAGE_F16)
+        lk.lk_build_pyramid(ctx, pyr, buf[:, :w], pitch=w + pad)
+        pyrs.append(pyr)
+        bufs.append(buf)
+    n = len(pts)
+    d_pts = torch.from_numpy(pts).cuda()
+    prm = lk.make_params(win, levels, 30, 0.01, 1e-6, 1.0)
+    out = lk.outputs(n, levels, with_iters=True)
+    lk.lk_track(ctx, pyrs[0], pyrs[1], d_pts, None, n, prm, *out)
+    torch.cuda.synchronize()
+    g = tuple(t.cpu().numpy() for t in out)
+    for pyr in pyrs:
+        lk.lk_pyramid_destroy(pyr)
+    r16 = oracle.track(p.prev, p.next, pts, win=win, levels=levels, fb_thresh=1.0, min_eig=1e-6, f16=True)
+    rp = oracle.track(p.prev, p.next, pts.astype(np.float64) + 1e-5, win=win, levels=levels, fb_thresh=1.0,
+                      min_eig=1e-6, f16=True)
+    rep = compare(*g, r16, r_perturbed=rp)
+    print(win, w, h, pad, rep)
+    assert rep.compared_ok >= 0.5 * n
