@@ -144,7 +144,8 @@ lk_result lk_build_pyramid(lk_context *ctx, lk_pyramid *pyr, const uint8_t *d_im
  * level count and storage).  h_pyrs, h_imgs, h_pitches are host arrays of n. */
 lk_result lk_build_pyramids(lk_context *ctx, lk_pyramid *const *h_pyrs, const uint8_t *const *h_imgs,
                             const int32_t *h_pitches, int32_t n, lk_stream stream);
-/* Copies level l (l >= 1) into d_dst as float32, row-major, width W_l
+/* Copies level l (0 <= l < levels; level 0 is the 8-bit frame of the last
+ * build, which must still exist) into d_dst as float32, row-major, width W_l
  * (diagnostics and tests).  For LK_STORAGE_F16 pyramids, d_grad (nullable)
  * receives the level's float32 (Gx, Gy) pairs, 2 W_l floats per row. */
 lk_result lk_pyramid_read_level(lk_context *ctx, const lk_pyramid *pyr, int32_t level, float *d_dst,

@@ -73,7 +73,9 @@ struct DownJob {
 struct Pyr12Job {
     const uint8_t *src;
     void *dst1, *dst2;
+    __half2 *g0, *g1;                 // binary16 storage: gradient planes of levels 0 and 1 (else null)
     int32_t spitch, pitch1, pitch2;   // elements per row
+    int32_t gpitch0, gpitch1;         // half2 elements per row of g0, g1
     int32_t sw, sh, w1, h1, w2, h2;
     int32_t f16;                      // levels stored as binary16
     int32_t tiles_x, tile_begin;
@@ -212,6 +214,7 @@ hipError_t launch_pool_reset(int32_t *d_count, int64_t *d_next_id, int n, hipStr
 // the best of each set.  d_wg_job[b] is the set of workgroup b.
 hipError_t launch_epipolar(const EpiJob *d_jobs, const int32_t *d_wg_job, int n_jobs, int total_wgs, double threshold,
                            hipStream_t stream);
-hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream);
+hipError_t launch_read_level(const LevelDesc &lv, int level, int storage, float *dst, float *dgrad,
+                             hipStream_t stream);
 
 }  // namespace lkmi

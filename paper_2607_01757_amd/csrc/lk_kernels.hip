@@ -234,7 +234,11 @@ __global__ __launch_bounds__(kThreads) void k_downsample_batched(const DownJob *
 
 // ------------------------------------------------ levels 1 and 2 in one pass
 //
-// Workgroup = one 32 x 16 tile of level 2 at (ox2, oy2).  Level 1 is formed
+// Workgroup = one 32 x 16 tile of level 2 at (ox2, oy2).  Binary16 storage
+// also writes the gradient planes of levels 0 and 1 for the 128 x 64 and
+// 64 x 32 blocks under the tile, from the staged bytes and the level-1
+// region (both gradients are exact before the binary16 rounding, so they
+// carry the bits of the gradient-plane kernel).  Level 1 is formed
 // on the region x1 in [2 ox2 - 2, 2 ox2 + 65), y1 in [2 oy2 - 2, 2 oy2 + 33)
 // (the 64 x 32 tile under the level-2 tile plus the two-pixel halo the
 // level-2 filter needs) from level 0 staged as bytes; the level-1 tile is
@@ -353,6 +357,63 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
             }
         }
     }
+    if constexpr (F16) {
+        // 2b. level-0 gradient plane of the 128 x 64 block at (4 ox2, 4 oy2):
+        //     thread = 4 columns x 8 rows; per staged row, the central
+        //     differences d and the [3 10 3] sums s of its 4 pixels (integers,
+        //     from the 6 bytes around them), slid down the rows:
+        //     Gx = (3 (d[-1] + d[+1]) + 10 d[0]) / 32, Gy = (s[+1] - s[-1]) / 32
+        const int c = 4 * (threadIdx.x & 31), r0 = 8 * (threadIdx.x >> 5);
+        const int x = 4 * ox2 + c, y0 = 4 * oy2 + r0;
+        // staged column of level-0 x is c + 16, staged row of y0 + k is r0 + 6 + k
+        auto row = [&](int k, int (&d)[4], int (&sr)[4]) {
+            const uint32_t *q = reinterpret_cast<const uint32_t *>(&sm.in[r0 + 6 + k][c + 12]);
+            const uint32_t wm = q[0], w0 = q[1], wp = q[2];
+            int p6[6];
+            p6[0] = (int)(wm >> 24);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) p6[m + 1] = (int)((w0 >> (8 * m)) & 0xFFu);
+            p6[5] = (int)(wp & 0xFFu);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                d[m] = p6[m + 2] - p6[m];
+                sr[m] = 3 * (p6[m] + p6[m + 2]) + 10 * p6[m + 1];
+            }
+        };
+        int dA[4], sA[4], dB[4], sB[4];
+        row(-1, dA, sA);
+        row(0, dB, sB);
+        for (int k = 0; k < 8; ++k) {
+            int dC[4], sC[4];
+            row(k + 1, dC, sC);
+            const int y = y0 + k;
+            if (y < j.sh && x < j.sw) {
+                __half2 g[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    g[m] = __floats2half2_rn((float)(3 * (dA[m] + dC[m]) + 10 * dB[m]) * 0.03125f,
+                                             (float)(sC[m] - sA[m]) * 0.03125f);
+                __half2 *dst = j.g0 + (size_t)y * j.gpitch0 + x;
+                if (x + 3 < j.sw) {
+                    uint4 u;
+                    u.x = __builtin_bit_cast(uint32_t, g[0]);
+                    u.y = __builtin_bit_cast(uint32_t, g[1]);
+                    u.z = __builtin_bit_cast(uint32_t, g[2]);
+                    u.w = __builtin_bit_cast(uint32_t, g[3]);
+                    *reinterpret_cast<uint4 *>(dst) = u;
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        if (x + m < j.sw) dst[m] = g[m];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                dA[m] = dB[m]; sA[m] = sB[m];
+                dB[m] = dC[m]; sB[m] = sC[m];
+            }
+        }
+    }
     __syncthreads();
     // 3. write the level-1 tile (region rows/columns 2 .. 33 / 2 .. 65): each
     //    thread stores 8 consecutive pixels of one row
@@ -386,9 +447,55 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
             }
         }
     }
+    const bool x_inside = rx1 >= 0 && rx1 + kP1W <= j.w1;
+    if constexpr (F16) {
+        // 3b. level-1 gradient plane of the 64 x 32 tile: thread = 4 columns x
+        //     2 rows; neighbours reflected into level 1 (reflect-101) where the
+        //     region reaches past it
+        const int c = 4 * (threadIdx.x & 15), r = 2 * (threadIdx.x >> 4);
+        const int x1 = rx1 + 2 + c, y1 = ry1 + 2 + r;
+        const bool y_in = ry1 >= 0 && ry1 + kP1H <= j.h1;
+        int cols[6], rows[4];
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            cols[m] = x_inside ? c + 1 + m : reflect101(clampi(x1 - 1 + m, -1, j.w1), j.w1) - rx1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            rows[m] = y_in ? r + 1 + m : reflect101(clampi(y1 - 1 + m, -1, j.h1), j.h1) - ry1;
+        float t[4][6];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int m = 0; m < 6; ++m) t[a][m] = sm.l1[rows[a]][cols[m]];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (y1 + k >= j.h1 || x1 >= j.w1) continue;
+            __half2 g[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const float gx = (3.0f * (t[k][m + 2] - t[k][m]) + 10.0f * (t[k + 1][m + 2] - t[k + 1][m])
+                                  + 3.0f * (t[k + 2][m + 2] - t[k + 2][m])) * 0.03125f;
+                const float gy = (3.0f * (t[k + 2][m] - t[k][m]) + 10.0f * (t[k + 2][m + 1] - t[k][m + 1])
+                                  + 3.0f * (t[k + 2][m + 2] - t[k][m + 2])) * 0.03125f;
+                g[m] = __floats2half2_rn(gx, gy);
+            }
+            __half2 *dst = j.g1 + (size_t)(y1 + k) * j.gpitch1 + x1;
+            if (x1 + 3 < j.w1) {
+                uint4 u;
+                u.x = __builtin_bit_cast(uint32_t, g[0]);
+                u.y = __builtin_bit_cast(uint32_t, g[1]);
+                u.z = __builtin_bit_cast(uint32_t, g[2]);
+                u.w = __builtin_bit_cast(uint32_t, g[3]);
+                *reinterpret_cast<uint4 *>(dst) = u;
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (x1 + m < j.w1) dst[m] = g[m];
+            }
+        }
+    }
     // 4. level-2 horizontal pass at the level-1 rows of the region; taps
     //    reflected into level 1 (identity away from its left and right edges)
-    const bool x_inside = rx1 >= 0 && rx1 + kP1W <= j.w1;
     for (int i = threadIdx.x; i < kP1H * kP12TileW; i += kThreads) {
         const int r = i / kP12TileW, c = i - r * kP12TileW;
         float v = 0.0f;
@@ -1624,13 +1731,16 @@ __global__ void k_write_descs(const PyrDescWrite *w, int n)
     if (i < n) *w[i].dst = w[i].desc;
 }
 
-// Level l >= 1 (and its gradient plane) as float, for diagnostics.
-__global__ __launch_bounds__(kThreads) void k_read_level(LevelDesc lv, int storage, float *dst, float *dgrad)
+// One level (and its gradient plane) as float, for diagnostics; kind: the
+// element type of the level (level 0 is 8-bit).
+__global__ __launch_bounds__(kThreads) void k_read_level(LevelDesc lv, int kind, float *dst, float *dgrad)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= lv.w * lv.h) return;
     const int y = i / lv.w, x = i - y * lv.w;
-    dst[i] = storage == LK_STORAGE_F16 ? ldpx<K_F16>(lv.img, y * lv.pitch + x) : ldpx<K_F32>(lv.img, y * lv.pitch + x);
+    dst[i] = kind == K_U8    ? ldpx<K_U8>(lv.img, y * lv.pitch + x)
+             : kind == K_F16 ? ldpx<K_F16>(lv.img, y * lv.pitch + x)
+                             : ldpx<K_F32>(lv.img, y * lv.pitch + x);
     if (dgrad && lv.grad) {
         const float2 g = __half22float2(lv.grad[y * lv.gpitch + x]);
         dgrad[2 * i] = g.x;
@@ -1804,11 +1914,13 @@ hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total
                                      : launch_track_batched_st<LK_STORAGE_F32>(d_items, n_items, b, stream);
 }
 
-hipError_t launch_read_level(const LevelDesc &lv, int storage, float *dst, float *dgrad, hipStream_t stream)
+hipError_t launch_read_level(const LevelDesc &lv, int level, int storage, float *dst, float *dgrad,
+                             hipStream_t stream)
 {
+    const int kind = level == 0 ? K_U8 : (storage == LK_STORAGE_F16 ? K_F16 : K_F32);
     const long n = (long)lv.w * lv.h;
     hipLaunchKernelGGL(k_read_level, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, stream,
-                       lv, storage, dst, dgrad);
+                       lv, kind, dst, dgrad);
     return hipGetLastError();
 }
 

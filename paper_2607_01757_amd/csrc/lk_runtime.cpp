@@ -182,6 +182,10 @@ void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<D
         j.spitch = d.lv[0].pitch; j.pitch1 = d.lv[1].pitch; j.pitch2 = d.lv[2].pitch;
         j.sw = d.lv[0].w; j.sh = d.lv[0].h; j.w1 = d.lv[1].w; j.h1 = d.lv[1].h; j.w2 = d.lv[2].w; j.h2 = d.lv[2].h;
         j.f16 = f16;
+        if (f16) {      // the fused launch also writes the gradient planes of levels 0 and 1
+            j.g0 = const_cast<__half2 *>(d.lv[0].grad); j.gpitch0 = d.lv[0].gpitch;
+            j.g1 = const_cast<__half2 *>(d.lv[1].grad); j.gpitch1 = d.lv[1].gpitch;
+        }
         j.tiles_x = (j.w2 + kP12TileW - 1) / kP12TileW;
         j.tile_begin = 0;
         p12->push_back(j);
@@ -198,7 +202,7 @@ void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<D
         down_by_level[l].push_back(j);
     }
     if (f16)
-        for (int l = 0; l < d.levels; ++l) {
+        for (int l = first == 3 ? 2 : 0; l < d.levels; ++l) {
             GradJob g{};
             g.src = d.lv[l].img; g.dst = const_cast<__half2 *>(d.lv[l].grad);
             g.spitch = d.lv[l].pitch; g.dpitch = d.lv[l].gpitch;
@@ -421,9 +425,10 @@ lk_result lk_pyramid_read_level(lk_context *ctx, const lk_pyramid *pyr, int32_t 
                                 lk_stream stream)
 {
     if (!ctx || !pyr || !d_dst) return fail(LK_ERR_INVALID_ARG, "ctx, pyr or d_dst is NULL");
-    if (level < 1 || level >= pyr->desc.levels) return fail(LK_ERR_INVALID_ARG, "level must be in [1, levels)");
+    if (level < 0 || level >= pyr->desc.levels) return fail(LK_ERR_INVALID_ARG, "level must be in [0, levels)");
+    if (!pyr->built) return fail(LK_ERR_INVALID_ARG, "pyramid was never built");
     (void)hipSetDevice(ctx->device);
-    hipError_t e = launch_read_level(pyr->desc.lv[level], pyr->desc.storage, d_dst, d_grad,
+    hipError_t e = launch_read_level(pyr->desc.lv[level], level, pyr->desc.storage, d_dst, d_grad,
                                      static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "read level launch");
 }

@@ -68,7 +68,7 @@ def test_pyramid_levels_and_gradients_f16(lk, ctx, gt, shape, levels):
     img = rng.integers(0, 256, size=shape).astype(np.uint8)
     p, t = gt.pyramid(img, levels, lk.LK_STORAGE_F16)
     ref, rgx, rgy = oracle.pyramid(img.astype(np.float64), levels, f16=True)
-    for l in range(1, levels):
+    for l in range(0, levels):
         h, w = ref[l].shape
         d = torch.empty((h, w), dtype=torch.float32, device="cuda")
         g = torch.empty((h, w, 2), dtype=torch.float32, device="cuda")
