@@ -157,8 +157,40 @@ class BatchedWorkload:
             self.lk.lk_pyramid_destroy(p)
 
 
+def settle(fn, seconds=0.15):
+    """Runs fn back to back for about `seconds` of device time, untimed: the
+    GPU's clock rises over the first tens of milliseconds of sustained work
+    (the tracker's kernel time falls from about 180 to 157 us over 25 ms), so
+    timed regions start from the steady clock a busy device runs at."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
+def prepared_step(lk, ctx, build_pyrs, build_imgs, pairs, pts, params, out, st, res):
+    """A graph-captured prepared step with the execution shape of the
+    committed table of tuned shapes (lk_exec_table.txt), or of the autotuner
+    when the table has no row for this batch."""
+    cfg, found = lk.lk_exec_table_lookup(ctx, pairs, params)
+    step = lk.lk_batch_create(ctx, build_pyrs, build_imgs, pairs, pts, None, params, out, st, res, None,
+                              config=None if found else lk.lk_exec_config(0, 0, 1, 0, 0, 0))
+    if found:
+        best, source = lk.lk_batch_config(step), "table"
+    else:
+        best, _ = lk.lk_batch_tune(step, reps=3)
+        source = "autotuner"
+    log("execution shape (%s): persistent=%d blocks_per_cu=%d chunk=%d waves_per_group=%d" % (
+        source, best.persistent, best.blocks_per_cu, best.chunk, best.waves_per_group))
+    return step, best, source
+
+
 def time_steps(fn, steps, warmup):
     import torch
+    settle(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -178,6 +210,7 @@ def time_block(fn, reps, warmup):
     """Mean duration of one call when `reps` calls run back to back, from two
     HIP events on the launch stream around the whole run."""
     import torch
+    settle(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -267,17 +300,16 @@ def run_batched(args):
     f_alg = flops_from_iters(iters, wl.win, False)
 
     # the step as one prepared batch: new-frame pyramids + all pairs, recorded
-    # into a HIP graph, execution shape chosen by the autotuner
-    step = lk.lk_batch_create(ctx, wl.next_pyr, wl.next_img, wl.pairs, wl.pts, None, wl.params, wl.out, wl.st,
-                              wl.res, None, config=lk.lk_exec_config(0, 4, 1, 0))
-    best, tuned_ms = lk.lk_batch_tune(step, reps=3)
-    log("autotuner: persistent=%d blocks_per_cu=%d (%.3f ms/step while tuning)" %
-        (best.persistent, best.blocks_per_cu, tuned_ms))
+    # into a HIP graph, execution shape from the committed table of tuned
+    # shapes (the autotuner runs here only when the table has no row for it)
+    step, best, shape_source = prepared_step(lk, ctx, wl.next_pyr, wl.next_img, wl.pairs, wl.pts, wl.params,
+                                             wl.out, wl.st, wl.res)
     # the tracker alone, same shape, for the roofline of the dominant kernel:
     # direct launches back to back (a graph replay per launch would add its
     # own gap to every kernel)
     trk = lk.lk_batch_create(ctx, [], [], wl.pairs, wl.pts, None, wl.params, wl.out, wl.st, wl.res, None,
-                             config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 0, 0))
+                             config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 0, best.chunk,
+                                                      best.waves_per_group, 0))
     t_trk = time_block(lambda: lk.lk_batch_run(trk), max(args.steps, 10), args.warmup)
     t_pyr = wl.time_build(max(args.steps, 10), args.warmup)
     wall, per = time_steps(lambda: lk.lk_batch_run(step), args.steps, args.warmup)
@@ -347,7 +379,8 @@ def run_batched(args):
                                "new-frame pyramids + all pairs in one graph-captured prepared batch",
                    "streams": len(streams), "keypoints_per_step": wl.n, "seed": args.seed,
                    "exec": {"persistent": best.persistent, "blocks_per_cu": best.blocks_per_cu,
-                            "use_graph": 1}},
+                            "chunk": best.chunk, "waves_per_group": best.waves_per_group, "use_graph": 1,
+                            "source": shape_source}},
         "p50_frame_ms": percentile(per, 50), "p99_frame_ms": percentile(per, 99),
         "tracked_fraction": float(np.mean(status == 0)),
         "roofline": {"bound": "alu", "kernel": "k_track_%s" % ("persist" if best.persistent else "batched"),
@@ -1060,11 +1093,10 @@ def run_sweep(args):
             pts = torch.from_numpy(np.concatenate([s.pts[:kp] for s in streams])).cuda()
             pairs = [(a, b, i * kp, kp) for i, (a, b) in enumerate(zip(wl.prev_pyr, wl.next_pyr))]
             out, st, res, _ = lk.outputs(n, 3)
-            step = lk.lk_batch_create(ctx, wl.next_pyr, wl.next_img, pairs, pts, None, wl.params, out, st, res,
-                                      None, config=lk.lk_exec_config(0, 4, 1, 0))
-            best, _ = lk.lk_batch_tune(step, reps=3)
+            step, best, _ = prepared_step(lk, ctx, wl.next_pyr, wl.next_img, pairs, pts, wl.params, out, st, res)
             trk = lk.lk_batch_create(ctx, [], [], pairs, pts, None, wl.params, out, st, res, None,
-                                     config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 0, 0))
+                                     config=lk.lk_exec_config(best.persistent, best.blocks_per_cu, 0, best.chunk,
+                                                      best.waves_per_group, 0))
             t_trk = time_block(lambda: lk.lk_batch_run(trk), reps, args.warmup)
             t_step = time_block(lambda: lk.lk_batch_run(step), reps, args.warmup)
 

@@ -214,7 +214,10 @@ lk_result lk_track_batched_noalloc(lk_context *ctx, const lk_pair *h_pairs, int3
  *     stealing from other XCDs when its own range is done);
  *   use_graph = 1: the whole step is recorded into a HIP graph at creation
  *     (and after lk_batch_tune) and replayed by lk_batch_run.
- * lk_batch_tune times every candidate shape on this batch (reps launches
+ *   waves_per_group (hardware dispatch): wavefronts per workgroup;
+ *   chunk (persistent grid): keypoints per work fetch.
+ * lk_batch_tune times every candidate shape on this batch (after about 20 ms
+ * of untimed steps that bring the device to its steady clock; reps launches
  * each, HIP events), keeps the fastest and returns it.  Creation and tuning
  * synchronize the device; lk_batch_run does not. */
 typedef struct {
@@ -234,9 +237,13 @@ typedef struct {
 } lk_batch_desc;
 
 typedef struct {
-    int32_t persistent;
-    int32_t blocks_per_cu;
-    int32_t use_graph;
+    int32_t persistent;                /* 0: hardware dispatch; 1: persistent grid */
+    int32_t blocks_per_cu;             /* persistent grid: workgroups per compute unit, 1..64 */
+    int32_t use_graph;                 /* 1: the step is recorded into a HIP graph and replayed */
+    int32_t chunk;                     /* persistent grid: keypoints a wavefront takes per fetch,
+                                          1..1024 (0: 16) */
+    int32_t waves_per_group;           /* hardware dispatch: wavefronts per workgroup, 0 (the
+                                          layout's default) or, for win 21 only, 1, 2 or 4 */
     int32_t reserved;                  /* must be 0 */
 } lk_exec_config;
 
@@ -248,6 +255,27 @@ lk_result lk_batch_run(lk_batch *b, lk_stream stream);
 lk_result lk_batch_tune(lk_batch *b, lk_stream stream, int32_t reps, lk_exec_config *best, float *best_ms);
 lk_result lk_batch_config(const lk_batch *b, lk_exec_config *cfg);
 lk_result lk_batch_destroy(lk_batch *b);   /* waits for the batch's work */
+
+/* Table of tuned execution shapes.  lk_batch_create with cfg == NULL takes
+ * the shape of the table row that matches the device's architecture (the
+ * gfx name before any ':'), the batch's win, levels and storage, and the
+ * buckets of its mean frame size and mean keypoint count per pair; with no
+ * matching row (or no pairs) it takes {0, 0, 1, 0, 0, 0}.  The table is read
+ * from the file named by the environment variable LKMI_EXEC_TABLE, else from
+ * lk_exec_table.txt in the directory of the library, when a lookup first
+ * sees that path (a missing file is an empty table; rows whose shape is not
+ * valid for their window are skipped).  Format: one row per line,
+ * "arch win levels storage res_bucket kp_bucket persistent blocks_per_cu
+ * use_graph chunk waves_per_group [ms_per_step]", '#' starts a comment.
+ *
+ * lk_exec_buckets: res_bucket of a mean level-0 pixel count per pair (0:
+ * below 400,000, 1: below 700,000, 2: below 1,500,000, 3: below 3,000,000,
+ * 4: above) and kp_bucket of a mean keypoint count per pair (0: below 256,
+ * 1: below 512, 2: below 1024, 3: below 2048, 4: above).  Host only.
+ * lk_exec_table_lookup: the shape lk_batch_create(cfg = NULL) would take for
+ * desc, *found = 1 if a table row matched. */
+lk_result lk_exec_buckets(int64_t mean_pixels, int32_t mean_points, int32_t *res_bucket, int32_t *kp_bucket);
+lk_result lk_exec_table_lookup(lk_context *ctx, const lk_batch_desc *desc, lk_exec_config *out, int32_t *found);
 
 /* ---- corner detection (Shi-Tomasi "good features to track") -------------
  * The paper's GFTT+LK front-end seeds and tops up its tracks with this

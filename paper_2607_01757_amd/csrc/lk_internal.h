@@ -196,12 +196,19 @@ hipError_t launch_track(const PyrDesc *d_prev, const PyrDesc *d_next, int storag
                         hipStream_t stream);
 hipError_t launch_write_desc(PyrDesc *d_dst, const PyrDesc &src, hipStream_t stream);
 hipError_t launch_write_descs(const PyrDescWrite *d_w, int n, hipStream_t stream);
+// waves_per_group: wavefronts per workgroup (0: the layout's default; other
+// values only where track_waves_supported says the kernel is built).
 hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total_points,
-                                const TrackArgs &a, int storage, hipStream_t stream);
-// Persistent tracker grid: blocks_per_cu workgroups per compute unit; 8
-// work counters at d_counters (zeroed by the launch itself).
+                                const TrackArgs &a, int storage, hipStream_t stream, int waves_per_group = 0);
+bool track_waves_supported(int win, int waves_per_group);
+// Persistent tracker grid: blocks_per_cu workgroups per compute unit, each
+// wavefront taking `chunk` keypoints per fetch; 8 work counters at
+// d_counters, kCounterStride ints apart (zeroed by the launch itself).
+constexpr int kCounterStride = 64;
+constexpr int kCounterBytes = 8 * kCounterStride * 4;
 hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
-                                   int storage, int *d_counters, int blocks_per_cu, int num_cus, hipStream_t stream);
+                                   int storage, int *d_counters, int blocks_per_cu, int num_cus, int chunk,
+                                   hipStream_t stream);
 // Detection of every frame in d_jobs (reset, peaks, selection: three launches).
 hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int radius,
                        int border, double quality, int min_dist, int max_corners, hipStream_t stream);

@@ -1666,14 +1666,15 @@ void k_track_batched(const BatchItem *items, int n_items, TrackArgs a)
     }
 }
 
-// Persistent form: a fixed grid whose wavefronts take keypoints from work
-// counters, one per XCD (XCD x first drains keypoints [x n/8, (x+1) n/8),
-// then helps the others).  Every wavefront leaves after one failed fetch per
+// Persistent form: a fixed grid whose wavefronts take chunks of `chunk`
+// consecutive keypoints from work counters, one per XCD, each in a 256-byte
+// slot of its own (XCD x first drains keypoints [x n/8, (x+1) n/8), then
+// helps the others).  Every wavefront leaves after one failed fetch per
 // counter, so the grid always drains.  The counters are zeroed by
 // k_reset_counters before each launch.
 template <int ST, class G>
 __global__ __launch_bounds__(G::WPB * 64) __attribute__((amdgpu_waves_per_eu(G::OCC)))
-void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *counters)
+void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *counters, int chunk)
 {
     __shared__ float s_lds[G::WPB * G::LDS];
     const int wib = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
@@ -1682,25 +1683,33 @@ void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *coun
         const int owner = (xcd + probe) & 7;
         const int first = (int)((long)a.n * owner / 8), end = (int)((long)a.n * (owner + 1) / 8);
         for (;;) {
-            // every lane takes part in the fetch (lane 0 adds 1, the others 0)
-            // so the index is never defined in a divergent branch; lane 0's
-            // old value is this wavefront's keypoint
-            const int w = __builtin_amdgcn_readfirstlane(atomicAdd(&counters[owner], lane == 0 ? 1 : 0));
-            const int wave = first + w;
-            if (wave >= end) break;
-            int lo = 0, hi = n_items - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (as_constant(items)[mid].first_wave <= wave) lo = mid; else hi = mid - 1;
-            }
-            lo = uniform_i(lo);
-            const BatchItem it = load_item(items, lo);
-            if (it.limit && wave - it.first_wave >= *as_constant(it.limit)) continue;
-            const int idx = (int)(it.pt_offset + (wave - it.first_wave));
-            if constexpr (G::CW == 1) {
-                [[clang::always_inline]] track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
-            } else {
-                track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
+            // every lane takes part in the fetch (lane 0 adds the chunk, the
+            // others 0) so the index is never defined in a divergent branch;
+            // lane 0's old value starts this wavefront's chunk
+            const int w = __builtin_amdgcn_readfirstlane(
+                atomicAdd(&counters[owner * kCounterStride], lane == 0 ? chunk : 0));
+            const int w0 = first + w;
+            if (w0 >= end) break;
+            const int w1 = min(w0 + chunk, end);
+            int lo = 0;
+            for (int wave = w0; wave < w1; ++wave) {
+                // items are ordered by first_wave: continue the search from
+                // the previous keypoint's item
+                int hi = n_items - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (as_constant(items)[mid].first_wave <= wave) lo = mid; else hi = mid - 1;
+                }
+                lo = uniform_i(lo);
+                const BatchItem it = load_item(items, lo);
+                if (it.limit && wave - it.first_wave >= *as_constant(it.limit)) continue;
+                const int idx = (int)(it.pt_offset + (wave - it.first_wave));
+                if constexpr (G::CW == 1) {
+                    [[clang::always_inline]] track_point<ST, G>(*it.prev, *it.next, a, idx, lane,
+                                                                s_lds + wib * G::LDS);
+                } else {
+                    track_point<ST, G>(*it.prev, *it.next, a, idx, lane, s_lds + wib * G::LDS);
+                }
             }
         }
     }
@@ -1708,7 +1717,7 @@ void k_track_persist(const BatchItem *items, int n_items, TrackArgs a, int *coun
 
 __global__ void k_reset_counters(int *c)
 {
-    if (threadIdx.x < 8) c[threadIdx.x] = 0;
+    if (threadIdx.x < 8) c[threadIdx.x * kCounterStride] = 0;
 }
 
 // Layouts: (CW, R) = (1, 7) for windows up to 21, (1, 16) up to 31; each
@@ -1720,6 +1729,9 @@ __global__ void k_reset_counters(int *c)
 // 0.243 with 8).
 using GeoW21 = Geo<1, 7, 21, 1, 4>;
 using GeoW21X = Geo<1, 7, 21, 1, 6, true>;     // win = 21 exactly: 80 registers, 6 wavefronts per SIMD
+using GeoW21X2 = Geo<1, 7, 21, 2, 6, true>;    // the same, 2 and 4 wavefronts per workgroup (tuner shapes)
+using GeoW21X4 = Geo<1, 7, 21, 4, 6, true>;
+using GeoW21XP = Geo<1, 7, 21, 1, 5, true>;    // persistent grid (its loop needs more registers than 6 waves allow)
 using GeoW31 = Geo<1, 16, 31, 4, 2>;
 
 // Copies pyramid descriptors into device memory, in stream order.
@@ -1778,13 +1790,18 @@ hipError_t launch_track_batched_g(const BatchItem *items, int n_items, const Tra
 }
 
 template <int ST>
-hipError_t launch_track_batched_st(const BatchItem *items, int n_items, const TrackArgs &a, hipStream_t s)
+hipError_t launch_track_batched_st(const BatchItem *items, int n_items, const TrackArgs &a, hipStream_t s, int wpg)
 {
     switch (choose_layout(a.win)) {
     case LAYOUT_W21:
-        return a.win == GeoW21X::WMAX ? launch_track_batched_g<ST, GeoW21X>(items, n_items, a, s)
-                                      : launch_track_batched_g<ST, GeoW21>(items, n_items, a, s);
-    case LAYOUT_W31: return launch_track_batched_g<ST, GeoW31>(items, n_items, a, s);
+        if (a.win != GeoW21X::WMAX) return wpg <= 1 ? launch_track_batched_g<ST, GeoW21>(items, n_items, a, s)
+                                                     : hipErrorInvalidValue;
+        if (wpg == 2) return launch_track_batched_g<ST, GeoW21X2>(items, n_items, a, s);
+        if (wpg == 4) return launch_track_batched_g<ST, GeoW21X4>(items, n_items, a, s);
+        return wpg <= 1 ? launch_track_batched_g<ST, GeoW21X>(items, n_items, a, s) : hipErrorInvalidValue;
+    case LAYOUT_W31:
+        return wpg == 0 || wpg == GeoW31::WPB ? launch_track_batched_g<ST, GeoW31>(items, n_items, a, s)
+                                               : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -1798,6 +1815,17 @@ int choose_layout(int win)
     if (win <= 21) return LAYOUT_W21;
     if (win <= LK_MAX_WIN) return LAYOUT_W31;
     return LAYOUT_NONE;
+}
+
+// Wavefronts per workgroup a batched tracker launch can take for `win`
+// (0: the layout's default): 1, 2 or 4 for the exact 21 x 21 build.
+bool track_waves_supported(int win, int wpg)
+{
+    if (wpg == 0) return choose_layout(win) != LAYOUT_NONE;
+    if (win == GeoW21X::WMAX) return wpg == 1 || wpg == 2 || wpg == 4;
+    if (choose_layout(win) == LAYOUT_W21) return wpg == 1;
+    if (choose_layout(win) == LAYOUT_W31) return wpg == GeoW31::WPB;
+    return false;
 }
 
 hipError_t launch_downsample(const DownJob &job, hipStream_t stream)
@@ -1870,48 +1898,56 @@ hipError_t launch_write_descs(const PyrDescWrite *d_w, int n, hipStream_t stream
 
 template <int ST, class G>
 hipError_t launch_track_persist_g(const BatchItem *items, int n_items, const TrackArgs &a, int *counters,
-                                  int grid, hipStream_t s)
+                                  int grid, int chunk, hipStream_t s)
 {
     const int need = (a.n + G::WPB - 1) / G::WPB;
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);
     hipLaunchKernelGGL((k_track_persist<ST, G>), dim3(grid < need ? grid : need), dim3(G::WPB * 64), 0, s, items,
-                       n_items, a, counters);
+                       n_items, a, counters, chunk);
     return hipGetLastError();
 }
 
 template <int ST>
 hipError_t launch_track_persist_st(const BatchItem *items, int n_items, const TrackArgs &a, int *counters,
-                                   int blocks_per_cu, int num_cus, hipStream_t s)
+                                   int blocks_per_cu, int num_cus, int chunk, hipStream_t s)
 {
+    const int grid = blocks_per_cu * num_cus;
     switch (choose_layout(a.win)) {
-    case LAYOUT_W21:      // (the exact build of the persistent kernel would spill at 6 wavefronts per SIMD)
-        return launch_track_persist_g<ST, GeoW21>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
+    case LAYOUT_W21:
+        return a.win == GeoW21X::WMAX
+                   ? launch_track_persist_g<ST, GeoW21XP>(items, n_items, a, counters, grid, chunk, s)
+                   : launch_track_persist_g<ST, GeoW21>(items, n_items, a, counters, grid, chunk, s);
     case LAYOUT_W31:
-        return launch_track_persist_g<ST, GeoW31>(items, n_items, a, counters, blocks_per_cu * num_cus, s);
+        return launch_track_persist_g<ST, GeoW31>(items, n_items, a, counters, grid, chunk, s);
     default:
         return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
-                                   int storage, int *d_counters, int blocks_per_cu, int num_cus, hipStream_t stream)
+                                   int storage, int *d_counters, int blocks_per_cu, int num_cus, int chunk,
+                                   hipStream_t stream)
+{
+    if (total_points <= 0) return hipSuccess;
+    if (chunk < 1) return hipErrorInvalidValue;
+    TrackArgs b = a;
+    b.n = total_points;
+    return storage == LK_STORAGE_F16
+               ? launch_track_persist_st<LK_STORAGE_F16>(d_items, n_items, b, d_counters, blocks_per_cu, num_cus,
+                                                         chunk, stream)
+               : launch_track_persist_st<LK_STORAGE_F32>(d_items, n_items, b, d_counters, blocks_per_cu, num_cus,
+                                                         chunk, stream);
+}
+
+hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
+                                int storage, hipStream_t stream, int waves_per_group)
 {
     if (total_points <= 0) return hipSuccess;
     TrackArgs b = a;
     b.n = total_points;
     return storage == LK_STORAGE_F16
-               ? launch_track_persist_st<LK_STORAGE_F16>(d_items, n_items, b, d_counters, blocks_per_cu, num_cus, stream)
-               : launch_track_persist_st<LK_STORAGE_F32>(d_items, n_items, b, d_counters, blocks_per_cu, num_cus, stream);
-}
-
-hipError_t launch_track_batched(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
-                                int storage, hipStream_t stream)
-{
-    if (total_points <= 0) return hipSuccess;
-    TrackArgs b = a;
-    b.n = total_points;
-    return storage == LK_STORAGE_F16 ? launch_track_batched_st<LK_STORAGE_F16>(d_items, n_items, b, stream)
-                                     : launch_track_batched_st<LK_STORAGE_F32>(d_items, n_items, b, stream);
+               ? launch_track_batched_st<LK_STORAGE_F16>(d_items, n_items, b, stream, waves_per_group)
+               : launch_track_batched_st<LK_STORAGE_F32>(d_items, n_items, b, stream, waves_per_group);
 }
 
 hipError_t launch_read_level(const LevelDesc &lv, int level, int storage, float *dst, float *dgrad,

@@ -29,6 +29,7 @@ ABI_SYMBOLS = (
     "lk_build_pyramid", "lk_build_pyramids", "lk_pyramid_read_level", "lk_track", "lk_track_batched",
     "lk_track_batched_noalloc",
     "lk_batch_create", "lk_batch_run", "lk_batch_tune", "lk_batch_config", "lk_batch_destroy",
+    "lk_exec_buckets", "lk_exec_table_lookup",
     "lk_server_create", "lk_server_open_stream", "lk_server_submit", "lk_server_poll", "lk_server_close_stream",
     "lk_server_get_stats", "lk_server_fail_next_launches", "lk_server_destroy",
     "lk_detector_create", "lk_detect_corners", "lk_detector_destroy",
@@ -59,7 +60,7 @@ class lk_batch_desc(C.Structure):
 
 class lk_exec_config(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("chunk", C.c_int32), ("waves_per_group", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lk_server_config(C.Structure):
@@ -145,6 +146,8 @@ def _load():
         "lk_batch_tune": (res, [vp, vp, i32, C.POINTER(lk_exec_config), C.POINTER(C.c_float)]),
         "lk_batch_config": (res, [vp, C.POINTER(lk_exec_config)]),
         "lk_batch_destroy": (res, [vp]),
+        "lk_exec_buckets": (res, [C.c_int64, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "lk_exec_table_lookup": (res, [vp, C.POINTER(lk_batch_desc), C.POINTER(lk_exec_config), C.POINTER(i32)]),
         "lk_server_create": (res, [vp, C.POINTER(lk_server_config), C.POINTER(vp)]),
         "lk_server_open_stream": (res, [vp, i32, i32, C.POINTER(C.c_uint32)]),
         "lk_server_submit": (res, [vp, C.c_uint32, vp, i32, vp, vp, i32, C.POINTER(C.c_uint64)]),
@@ -311,6 +314,24 @@ def lk_batch_create(ctx, build_pyrs, build_imgs, pairs, pts, guess, params: lk_p
     h = C.c_void_p()
     _check(lib.lk_batch_create(ctx, C.byref(d), C.byref(config) if config is not None else None, C.byref(h)))
     return h
+
+
+def lk_exec_buckets(mean_pixels: int, mean_points: int):
+    rb, kb = C.c_int32(), C.c_int32()
+    _check(lib.lk_exec_buckets(int(mean_pixels), int(mean_points), C.byref(rb), C.byref(kb)))
+    return rb.value, kb.value
+
+
+def lk_exec_table_lookup(ctx, pairs, params: lk_params):
+    """The tuned shape lk_batch_create(config=None) would take for these
+    pairs: (lk_exec_config, found)."""
+    arr = (lk_pair * max(len(pairs), 1))()
+    for i, (a, b, off, n) in enumerate(pairs):
+        arr[i].prev, arr[i].next, arr[i].pt_offset, arr[i].n, arr[i].reserved = _hv(a), _hv(b), off, n, 0
+    d = lk_batch_desc(0, None, None, None, len(pairs), arr, None, None, params, None, None, None, None)
+    cfg, found = lk_exec_config(), C.c_int32()
+    _check(lib.lk_exec_table_lookup(ctx, C.byref(d), C.byref(cfg), C.byref(found)))
+    return cfg, bool(found.value)
 
 
 def lk_batch_run(batch, stream=None):

@@ -59,7 +59,7 @@ def test_struct_sizes_match_the_header(lk):
     # the ctypes mirrors must have the C layout (checked by size)
     assert C.sizeof(lk.lk_params) == 32
     assert C.sizeof(lk.lk_pair) == 32
-    assert C.sizeof(lk.lk_exec_config) == 16
+    assert C.sizeof(lk.lk_exec_config) == 24
     assert C.sizeof(lk.lk_timing) == 24
 
 
@@ -89,3 +89,18 @@ def test_params_check_other_ranges(lk):
         lk.lk_params_check(lk.make_params(**good), 0)
     with pytest.raises(lk.LKError):
         lk.lk_params_check(lk.make_params(**good), 9)
+
+
+def test_exec_buckets_boundaries():
+    """Buckets of the tuned-shape table (host only)."""
+    from paper_2607_01757_amd import lk
+    assert lk.lk_exec_buckets(0, 0) == (0, 0)
+    assert lk.lk_exec_buckets(640 * 480, 150) == (0, 0)
+    assert lk.lk_exec_buckets(399999, 255) == (0, 0)
+    assert lk.lk_exec_buckets(400000, 256) == (1, 1)
+    assert lk.lk_exec_buckets(960 * 600, 700) == (1, 2)
+    assert lk.lk_exec_buckets(1280 * 720, 1023) == (2, 2)
+    assert lk.lk_exec_buckets(1920 * 1080, 1500) == (3, 3)
+    assert lk.lk_exec_buckets(3000000, 2048) == (4, 4)
+    with pytest.raises(lk.LKError):
+        lk.lk_exec_buckets(-1, 0)

@@ -15,7 +15,7 @@ STRUCTS = {
     "lk_pair": ["prev", "next", "pt_offset", "n", "reserved"],
     "lk_batch_desc": ["n_builds", "build_pyrs", "build_imgs", "build_pitches", "n_pairs", "pairs", "d_pts",
                       "d_guess", "params", "d_out_pts", "d_status", "d_residual", "d_iters"],
-    "lk_exec_config": ["persistent", "blocks_per_cu", "use_graph", "reserved"],
+    "lk_exec_config": ["persistent", "blocks_per_cu", "use_graph", "chunk", "waves_per_group", "reserved"],
     "lk_server_config": ["max_streams", "max_points", "levels", "storage", "params", "max_batch", "inflight",
                          "queue_depth", "reserved", "hbm_budget_bytes"],
     "lk_timing": ["submit_ns", "launch_ns", "done_ns"],

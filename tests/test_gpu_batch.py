@@ -86,13 +86,19 @@ def test_batched_equals_plain_bitwise(lk, ctx, storage, win, levels, fb):
     st.close()
 
 
-@pytest.mark.parametrize("persistent,bpc,graph", [(0, 0, 0), (0, 0, 1), (1, 1, 1), (1, 4, 0), (1, 16, 1)])
-def test_prepared_batch_equals_plain(lk, ctx, persistent, bpc, graph):
+@pytest.mark.parametrize("persistent,bpc,graph,chunk,wpg,storage",
+                         [(0, 0, 0, 0, 0, 0), (0, 0, 1, 0, 0, 0), (1, 1, 1, 0, 0, 0), (1, 4, 0, 1, 0, 0),
+                          (1, 16, 1, 32, 0, 0), (1, 20, 0, 8, 0, 1), (0, 0, 1, 0, 2, 0), (0, 0, 0, 0, 4, 0),
+                          (0, 0, 1, 0, 4, 1), (0, 0, 0, 0, 1, 1)])
+def test_prepared_batch_equals_plain(lk, ctx, persistent, bpc, graph, chunk, wpg, storage):
+    """Every execution shape the tuner can pick (hardware dispatch with 1, 2
+    or 4 wavefronts per workgroup, persistent grids with fine and coarse work
+    fetches) gives the plain path's bits."""
     import torch
-    st = Setup(lk, ctx, make_streams(7), 0, 21, 3, 1.0)
+    st = Setup(lk, ctx, make_streams(7 + storage), storage, 21, 3, 1.0)
     ref = st.plain()
     out = st.outputs()
-    cfg = lk.lk_exec_config(persistent, bpc, graph, 0)
+    cfg = lk.lk_exec_config(persistent, bpc, graph, chunk, wpg, 0)
     b = lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, st.params, *out, config=cfg)
     for rep in range(3):
         for t in out:
@@ -128,9 +134,12 @@ def test_autotuner_picks_a_config_and_keeps_results(lk, ctx):
 def test_invalid_batch_arguments(lk, ctx):
     st = Setup(lk, ctx, make_streams(1, n=2), 0, 21, 3, 0.0)
     out = st.outputs()
-    with pytest.raises(lk.LKError):
-        lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, st.params, *out,
-                           config=lk.lk_exec_config(2, 1, 0, 0))
+    for bad_cfg in (lk.lk_exec_config(2, 1, 0, 0), lk.lk_exec_config(0, 0, 1, 0, 3, 0),
+                    lk.lk_exec_config(1, 4, 1, 0, 2, 0), lk.lk_exec_config(1, 4, 1, 2000, 0, 0),
+                    lk.lk_exec_config(0, 0, 1, 0, 0, 1)):
+        with pytest.raises(lk.LKError) as e:
+            lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, st.params, *out, config=bad_cfg)
+        assert e.value.code == lk.LK_ERR_INVALID_ARG
     bad = lk.make_params(win=22)
     with pytest.raises(lk.LKError):
         lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, bad, *out)
@@ -168,3 +177,40 @@ def test_batched_build_writes_every_descriptor(lk, ctx, levels_of):
         assert (ref[1].cpu().numpy() == 0).mean() > 0.5
     for p in pp + pn + qn:
         lk.lk_pyramid_destroy(p)
+
+
+def test_shape_table_row_is_used(lk, ctx, tmp_path, monkeypatch):
+    """lk_batch_create without a shape takes the matching row of the table
+    file (architecture, window, levels, storage, size and keypoint buckets),
+    and the step keeps the plain path's bits; rows for other keys, comments
+    and malformed lines are skipped."""
+    import torch
+    st = Setup(lk, ctx, make_streams(5, n=6), 0, 21, 3, 0.0)
+    ref = st.plain()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    px = int(np.mean([w * h for (w, h) in [(s.width, s.height) for s in make_streams(5, n=6)]]))
+    kp = int(np.mean(st.counts))
+    rb, kb = lk.lk_exec_buckets(px, kp)
+    table = tmp_path / "table.txt"
+    table.write_text("# arch win levels storage res kp persistent bpc graph chunk wpg ms\n"
+                     "%s 21 3 0 %d %d 1 7 1 5 0 0.5\n"
+                     "%s 21 3 1 %d %d 0 0 1 0 2\n"
+                     "not a row\n"
+                     "%s 9 3 0 %d %d 0 0 1 0 4\n" % (arch, rb, kb, arch, rb, kb, arch, rb, kb))
+    monkeypatch.setenv("LKMI_EXEC_TABLE", str(table))
+    cfg, found = lk.lk_exec_table_lookup(ctx, st.pairs, st.params)
+    assert found and (cfg.persistent, cfg.blocks_per_cu, cfg.use_graph, cfg.chunk, cfg.waves_per_group) == \
+        (1, 7, 1, 5, 0)
+    out = st.outputs()
+    b = lk.lk_batch_create(ctx, st.pn, st.next, st.pairs, st.pts, None, st.params, *out)
+    got = lk.lk_batch_config(b)
+    assert (got.persistent, got.blocks_per_cu, got.chunk) == (1, 7, 5)
+    lk.lk_batch_run(b)
+    torch.cuda.synchronize()
+    same(ref, [t.cpu().numpy() for t in out])
+    lk.lk_batch_destroy(b)
+    # another window: no row matches, the default shape
+    cfg, found = lk.lk_exec_table_lookup(ctx, st.pairs, lk.make_params(win=15))
+    assert not found and (cfg.persistent, cfg.use_graph, cfg.waves_per_group) == (0, 1, 0)
+    monkeypatch.delenv("LKMI_EXEC_TABLE")
+    st.close()
