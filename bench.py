@@ -245,7 +245,7 @@ def profiled_traffic(kernel, summary="profiles/hbm_counters_batched64.txt",
     return None
 
 
-def cpu_baseline(streams, n_sample, win, levels, fb, n_sample_1t=6):
+def cpu_baseline(streams, n_sample, win, levels, fb, n_sample_1t=16):
     """The FP64 oracle timed on the host: on every core over n_sample streams,
     and on one thread over the first n_sample_1t of them."""
     import oracle

@@ -1488,25 +1488,40 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
         int jbx = uniform_i(cix + (int)fminf(fmaxf(floorf(cfx + gx), lox), hix));
         int jby = uniform_i(ciy + (int)fminf(fmaxf(floorf(cfy + gy), loy), hiy));
         load_target(jbx, jby);
+        // The cell [fbx, fbx + 1) x [fby, fby + 1) of the loaded taps (level
+        // coordinates relative to c, exact small integers).  While an estimate
+        // stays in it, its integer part is the loaded one, and when the cell
+        // lies inside the in-bounds box the estimate is in bounds: four
+        // compares stand in for the bounds test, the floors, the conversions
+        // and the base comparison (the clamped first base holds no estimate
+        // outside the box, so the first iteration takes the full test then).
+        float fbx = (float)(jbx - cix), fby = (float)(jby - ciy);
+        float fbx1 = fbx + 1.0f, fby1 = fby + 1.0f;
+        bool cell_in = fbx1 <= hix && fby1 <= hiy;         // fbx >= lox, fby >= loy by the clamp
         dx = 0.0f; dy = 0.0f;
         int k = 0;
         bool oob = false;
         while (k < a.max_iters) {
             ++k;
             const float ux = (cfx + gx) + dx, uy = (cfy + gy) + dy;
-            if (!(ux >= lox && ux <= hix && uy >= loy && uy <= hiy)) {
-                oob = true;          // the window left the level before this step
-                break;
-            }
-            const float fux = floorf(ux), fuy = floorf(uy);
-            const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
-            if (bx != jbx || by != jby) {
-                load_target(bx, by);
-                jbx = bx; jby = by;
+            if (!(cell_in && ux >= fbx && ux < fbx1 && uy >= fby && uy < fby1)) {
+                if (!(ux >= lox && ux <= hix && uy >= loy && uy <= hiy)) {
+                    oob = true;          // the window left the level before this step
+                    break;
+                }
+                const float fux = floorf(ux), fuy = floorf(uy);
+                const int bx = uniform_i(cix + (int)fux), by = uniform_i(ciy + (int)fuy);
+                if (bx != jbx || by != jby) {
+                    load_target(bx, by);
+                    jbx = bx; jby = by;
+                }
+                fbx = fux; fby = fuy;
+                fbx1 = fbx + 1.0f; fby1 = fby + 1.0f;
+                cell_in = fbx >= lox && fbx1 <= hix && fby >= loy && fby1 <= hiy;
             }
             float bxs = 0.0f, bys = 0.0f;
             if constexpr (CW == 1) {
-                const float ax = ux - fux, ay = uy - fuy;
+                const float ax = ux - fbx, ay = uy - fby;
                 float h0 = lerp_row(ax, jt[0][0], jt[0][1]);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
@@ -1517,7 +1532,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
                     h0 = h1;
                 }
             } else {
-                const Weights w = bilinear_weights(ux - fux, uy - fuy);
+                const Weights w = bilinear_weights(ux - fbx, uy - fby);
 #pragma unroll
                 for (int i = 0; i < R; ++i)
 #pragma unroll
