@@ -12,7 +12,8 @@ import ctypes as C
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "liblkmi.so")
+# LKMI_LIB: another build of the library (e.g. one with host-side sanitizers)
+LIB_PATH = os.environ.get("LKMI_LIB") or os.path.join(PKG, "liblkmi.so")
 
 LK_SUCCESS, LK_ERR_INVALID_ARG, LK_ERR_OUT_OF_MEMORY, LK_ERR_DEVICE = 0, 1, 2, 3
 LK_ERR_BUSY, LK_ERR_NOT_READY, LK_ERR_NOT_FOUND, LK_ERR_NOT_IMPLEMENTED = 4, 5, 6, 7
