@@ -261,6 +261,10 @@ struct alignas(16) P12Smem {
     float l1[kP1H][kP1W + 1];
 };
 
+// Two 16-bit unsigned integers in one register (packed 16-bit adds).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+
 __device__ __forceinline__ float to_storage(float v, bool f16)
 {
     return f16 ? __half2float(__float2half_rn(v)) : v;
@@ -328,32 +332,34 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
             // On 8-bit data the binomial filter is exact in float (see
             // binom5), so it is formed here in integers: the horizontal sums
             // (weights 1 4 6 4 1, at most 255 x 16) and the vertical sum of
-            // five of them (at most 255 x 256), then one conversion and the
-            // scaling by 1 / 256, both exact: the same bits as binom5 twice.
-            auto hsum2 = [&](int row, uint32_t &a, uint32_t &b) {
+            // five of them (at most 255 x 256 = 65280), then one conversion
+            // and the scaling by 1 / 256, both exact: the same bits as binom5
+            // twice.  Both columns of the pair go through the sums at once, as
+            // the two 16-bit halves of one register (packed 16-bit integer
+            // adds; every sum fits 16 bits): the byte permutes place tap k of
+            // column c and tap k + 2 of column c + 1 side by side.
+            auto hsum2 = [&](int row) {
                 const uint32_t *q = col + row * (kP0W / 4);
                 const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
-                const uint32_t t2 = (w0 >> 16) & 0xFFu, t3 = w0 >> 24, t4 = w1 & 0xFFu, t5 = (w1 >> 8) & 0xFFu;
-                const uint32_t t6 = (w1 >> 16) & 0xFFu, t7 = w1 >> 24, t8 = w2 & 0xFFu;
-                a = (t2 + t6) + 4u * (t3 + t5) + 6u * t4;
-                b = (t4 + t8) + 4u * (t5 + t7) + 6u * t6;
+                const u16x2 p0 = as_u16x2(__builtin_amdgcn_perm(w1, w0, 0x0c040c02u));   // t2 | t4
+                const u16x2 p1 = as_u16x2(__builtin_amdgcn_perm(w1, w0, 0x0c050c03u));   // t3 | t5
+                const u16x2 p2 = as_u16x2(__builtin_amdgcn_perm(w1, w0, 0x0c060c04u));   // t4 | t6
+                const u16x2 p3 = as_u16x2(__builtin_amdgcn_perm(w1, w0, 0x0c070c05u));   // t5 | t7
+                const u16x2 p4 = as_u16x2(__builtin_amdgcn_perm(w2, w1, 0x0c040c02u));   // t6 | t8
+                return (p0 + p4) + (u16x2)4 * (p1 + p3) + (u16x2)6 * p2;
             };
-            auto vsum = [](uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3, uint32_t s4) {
-                return (float)((s0 + s4) + 4u * (s1 + s3) + 6u * s2) * (1.0f / 256.0f);
+            auto vsum = [](u16x2 s0, u16x2 s1, u16x2 s2, u16x2 s3, u16x2 s4) {
+                const uint32_t v = __builtin_bit_cast(uint32_t, (s0 + s4) + (u16x2)4 * (s1 + s3) + (u16x2)6 * s2);
+                return make_float2((float)(v & 0xFFFFu) * (1.0f / 256.0f), (float)(v >> 16) * (1.0f / 256.0f));
             };
             // output row r uses level-0 staged rows 2 r .. 2 r + 4
-            uint32_t a0, b0, a1, b1, a2, b2;
-            hsum2(2 * r_lo, a0, b0);
-            hsum2(2 * r_lo + 1, a1, b1);
-            hsum2(2 * r_lo + 2, a2, b2);
+            u16x2 h0 = hsum2(2 * r_lo), h1 = hsum2(2 * r_lo + 1), h2 = hsum2(2 * r_lo + 2);
             for (int r = r_lo; r < r_hi; ++r) {
-                uint32_t a3, b3, a4, b4;
-                hsum2(2 * r + 3, a3, b3);
-                hsum2(2 * r + 4, a4, b4);
-                sm.l1[r][c] = to_storage(vsum(a0, a1, a2, a3, a4), f16);
-                sm.l1[r][c + 1] = to_storage(vsum(b0, b1, b2, b3, b4), f16);
-                a0 = a2; a1 = a3; a2 = a4;
-                b0 = b2; b1 = b3; b2 = b4;
+                const u16x2 h3 = hsum2(2 * r + 3), h4 = hsum2(2 * r + 4);
+                const float2 v = vsum(h0, h1, h2, h3, h4);
+                sm.l1[r][c] = to_storage(v.x, f16);
+                sm.l1[r][c + 1] = to_storage(v.y, f16);
+                h0 = h2; h1 = h3; h2 = h4;
             }
         }
     }
