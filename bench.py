@@ -386,8 +386,8 @@ def run_batched(args):
         "roofline": {"bound": "alu", "kernel": "k_track_%s" % ("persist" if best.persistent else "batched"),
                      "achieved": f_alg / t_trk / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": f_alg / t_trk / 1e12 / PEAK_FP32_TFLOPS,
-                     # counters were taken for the float32-storage instantiation only
-                     "traffic": None if f16 else profiled_traffic("k_track_batched"),
+                     "traffic": profiled_traffic("k_track_batched", summary="profiles/hbm_counters_batched64%s.txt"
+                                                 % ("_f16" if f16 else "")),
                      "flops_per_launch": f_alg, "kernel_ms": t_trk * 1e3},
         "path_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": b_alg / step_s / 1e9,
                      "frac": b_alg / step_s / 1e9 / PEAK_HBM_GBS,
