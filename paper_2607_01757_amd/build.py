@@ -16,7 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblkmi.so")
-SOURCES = ["lk_kernels.hip", "lk_gftt.hip", "lk_pool_kernels.hip", "lk_runtime.cpp", "lk_batch.cpp", "lk_server.cpp",
+SOURCES = ["lk_kernels.hip", "lk_gftt.hip", "lk_pool_kernels.hip", "lk_errors.cpp", "lk_runtime.cpp", "lk_batch.cpp",
+           "lk_sched.cpp", "lk_server.cpp",
            "lk_detector.cpp", "lk_pool.cpp", "lk_epipolar_kernels.hip", "lk_epipolar.cpp"]
 ARCH = os.environ.get("LKMI_ARCH", "gfx950")
 

@@ -16,30 +16,13 @@ using namespace lkmi;
 
 // ------------------------------------------------------------------ errors
 
-namespace {
-thread_local std::string g_last_error;
-}
-
 namespace lkmi {
-
-lk_result fail(lk_result code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
 
 lk_result hip_fail(hipError_t e, const char *what)
 {
     return fail(e == hipErrorOutOfMemory ? LK_ERR_OUT_OF_MEMORY : LK_ERR_DEVICE, "%s: %s", what,
                 hipGetErrorString(e));
 }
-
-void clear_error() { g_last_error.clear(); }
 
 // ------------------------------------------------------------------ staging
 
@@ -235,8 +218,6 @@ lk_params lk_params_default(void)
     p.eps = 0.01f; p.min_eig = 1e-6f; p.fb_thresh = 0.0f; p.reserved = 0;
     return p;
 }
-
-const char *lk_last_error(void) { return g_last_error.c_str(); }
 
 lk_result lk_context_create(int32_t device, uint64_t hbm_budget_bytes, lk_context **out)
 {

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <vector>
 
+#include "lk_error.h"
 #include "lk_internal.h"
 
 // Pinned host + device buffer pairs used to ship small tables (batch items,
@@ -70,9 +71,7 @@ void make_build_tables(lk_pyramid *const *pyrs, int n, BuildTables *t);
 // Enqueues the build from tables already in device memory at d_base.
 hipError_t launch_build_tables(const BuildTables &t, const char *d_base, hipStream_t s);
 
-lk_result fail(lk_result code, const char *fmt, ...);
 lk_result hip_fail(hipError_t e, const char *what);
-void clear_error();
 int level_dims(int w, int h, int levels, int32_t *ws, int32_t *hs);
 lk_result check_params(const lk_params *p, int pyr_levels);
 lk_result check_pair(const lk_context *ctx, const lk_pyramid *prev, const lk_pyramid *next, int idx);
