@@ -8,7 +8,11 @@
 //                     LDS slab (entry (r, c) of lane l at [(9 r + c) 64 + l],
 //                     so the lanes of a wavefront hit distinct banks), the
 //                     null vector is mapped to pixel space and every
-//                     correspondence of the set is scored;
+//                     correspondence of the set is scored; the set's
+//                     correspondences are staged in LDS, 512 at a time, by
+//                     the whole wavefront, and every lane reads each one
+//                     from there (one broadcast read, no memory round trip
+//                     per correspondence);
 //   k_epi_best        one workgroup per set: the best hypothesis (most
 //                     inliers, lowest index on ties), its model solved again
 //                     by the same code (same bits), and its inlier mask.
@@ -21,6 +25,7 @@ namespace lkmi {
 namespace {
 
 constexpr int kEpiLanes = 64;
+constexpr int kEpiChunk = 512;             // correspondences staged in LDS at a time
 constexpr double kEpiRankTol = 1e-10;
 
 __device__ __forceinline__ double &slab(double *sa, int r, int c, int lane)
@@ -156,27 +161,44 @@ __device__ __forceinline__ bool epi_inlier(const double (&F)[9], float px, float
     const double l2 = F[6] * x + F[7] * y + F[8];
     const double num = (double)qx * l0 + (double)qy * l1 + l2;
     const double den = l0 * l0 + l1 * l1;
-    return den > 0.0 && num * num <= thr2 * den;
+    return (den > 0.0) & (num * num <= thr2 * den);
 }
 
-__global__ __launch_bounds__(kEpiLanes) void k_epi_hypotheses(const EpiJob *jobs, const int32_t *wg_job, double thr2)
+__global__ __launch_bounds__(kEpiLanes) void k_epi_hypotheses(const EpiJob *__restrict__ jobs,
+                                                              const int32_t *__restrict__ wg_job, double thr2)
 {
     __shared__ double sa[72 * kEpiLanes];
     __shared__ int scol[9 * kEpiLanes];
+    __shared__ float4 spq[kEpiChunk];
     const int lane = threadIdx.x;
-    const EpiJob &J = jobs[wg_job[blockIdx.x]];
+    const EpiJob &J = jobs[__builtin_amdgcn_readfirstlane(wg_job[blockIdx.x])];
+    const int n = __builtin_amdgcn_readfirstlane(J.n);
     const int k = (blockIdx.x - J.wg_begin) * kEpiLanes + lane;
-    if (k >= J.h) return;                      // no barriers below: lanes work alone
+    const bool live = k < J.h;
     double F[9];
-    int cnt = -1;
-    if (epi_model(J, J.samples + 8 * k, sa, scol, lane, F)) {
-        cnt = 0;
-        for (int i = 0; i < J.n; ++i) cnt += epi_inlier(F, J.p[2 * i], J.p[2 * i + 1], J.q[2 * i], J.q[2 * i + 1], thr2);
+    // every lane stays to the end: the whole wavefront stages the correspondences
+    const bool ok = live && epi_model(J, J.samples + 8 * k, sa, scol, lane, F);
+    int cnt = 0;
+    for (int i0 = 0; i0 < n; i0 += kEpiChunk) {
+        const int m = min(kEpiChunk, n - i0);
+        __syncthreads();                       // every lane has read the previous chunk
+        for (int i = lane; i < m; i += kEpiLanes) {
+            const int g = i0 + i;
+            spq[i] = make_float4(J.p[2 * g], J.p[2 * g + 1], J.q[2 * g], J.q[2 * g + 1]);
+        }
+        __syncthreads();
+        if (ok) {
+#pragma unroll 4
+            for (int i = 0; i < m; ++i) {
+                const float4 v = spq[i];
+                cnt += epi_inlier(F, v.x, v.y, v.z, v.w, thr2);
+            }
+        }
     }
-    J.counts[k] = cnt;
+    if (live) J.counts[k] = ok ? cnt : -1;
 }
 
-__global__ __launch_bounds__(kEpiLanes) void k_epi_best(const EpiJob *jobs, double thr2)
+__global__ __launch_bounds__(kEpiLanes) void k_epi_best(const EpiJob *__restrict__ jobs, double thr2)
 {
     __shared__ double sa[72 * kEpiLanes];
     __shared__ int scol[9 * kEpiLanes];
