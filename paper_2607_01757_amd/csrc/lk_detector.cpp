@@ -14,10 +14,11 @@ struct lk_detector {
     lk_context *ctx = nullptr;
     int32_t max_frames = 0;
     int64_t max_pixels = 0;
-    void *d_ws = nullptr;            // per-frame counters and maxima, then peaks, then candidates
+    void *d_ws = nullptr;            // per-frame counters, maxima and histograms, then peaks, then candidates
     size_t bytes = 0;
     int32_t *d_counts = nullptr;     // n_peaks of frame f at [2 f], n_cand at [2 f + 1]
     unsigned long long *d_max = nullptr;
+    uint32_t *d_hist = nullptr;      // 256 bins per frame
     GfttPeak *d_peaks = nullptr;
     GfttPeak *d_cand = nullptr;
 };
@@ -58,6 +59,7 @@ lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const l
         J.cand = det->d_cand + pixels;
         J.n_cand = det->d_counts + 2 * f + 1;
         J.max_bits = det->d_max + f;
+        J.hist = det->d_hist + 256 * (size_t)f;
         pixels += (int64_t)J.w * J.h;
         tiles += (long long)J.tiles_x * ((J.h + kGfttTileH - 1) / kGfttTileH);
     }
@@ -101,7 +103,9 @@ lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pi
     const size_t cnt_bytes = ((size_t)max_frames * 2 * sizeof(int32_t) + 255) & ~size_t(255);
     const size_t max_off = cnt_bytes;
     const size_t max_bytes = ((size_t)max_frames * sizeof(unsigned long long) + 255) & ~size_t(255);
-    const size_t peaks_off = max_off + max_bytes;
+    const size_t hist_off = max_off + max_bytes;
+    const size_t hist_bytes = (size_t)max_frames * 256 * sizeof(uint32_t);
+    const size_t peaks_off = hist_off + hist_bytes;
     const size_t cand_off = peaks_off + (size_t)max_pixels * sizeof(GfttPeak);
     const size_t bytes = cand_off + (size_t)max_pixels * sizeof(GfttPeak);
     if (ctx->budget && ctx->in_use.load() + bytes > ctx->budget)
@@ -117,6 +121,7 @@ lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pi
     d->bytes = bytes;
     d->d_counts = static_cast<int32_t *>(d->d_ws);
     d->d_max = reinterpret_cast<unsigned long long *>(static_cast<char *>(d->d_ws) + max_off);
+    d->d_hist = reinterpret_cast<uint32_t *>(static_cast<char *>(d->d_ws) + hist_off);
     d->d_peaks = reinterpret_cast<GfttPeak *>(static_cast<char *>(d->d_ws) + peaks_off);
     d->d_cand = reinterpret_cast<GfttPeak *>(static_cast<char *>(d->d_ws) + cand_off);
     ctx->in_use += bytes;

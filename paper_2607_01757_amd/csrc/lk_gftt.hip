@@ -331,9 +331,12 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
                                                        int min_dist)
 {
     __shared__ uint32_t s_cnt[BLOCK / 64], s_base;
+    __shared__ uint32_t s_hist[256];
     __shared__ OccGridSmem s_grid;
     const GfttJob &J = jobs[blockIdx.y];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    static_assert(BLOCK == 256, "one histogram bin per thread");
+    s_hist[threadIdx.x] = 0u;
     const int np = *J.n_peaks;
     // peaks that a cached occupied point blocks can never be selected: they
     // are dropped here (the selection still checks every occupied point)
@@ -348,8 +351,16 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
         const int y = (int)(p.idx / (uint32_t)W), x = (int)p.idx - y * W;
         return !occ_grid_blocked(G, s_grid, x, y, md2d);
     };
-    const double thr = quality * __longlong_as_double((long long)*J.max_bits);
+    const unsigned long long max_bits = *J.max_bits;
+    const double thr = quality * __longlong_as_double((long long)max_bits);
     const unsigned long long thr_bits = (unsigned long long)__double_as_longlong(thr);
+    // the candidates' R bits lie in (thr_bits, max_bits]: they share the
+    // leading d0 bytes of those two, and byte d0 is histogrammed for the
+    // selection's first radix pass
+    const unsigned long long diff = max_bits ^ thr_bits;
+    const int d0 = diff ? (__clzll((long long)diff) >> 3) : 8;
+    const int hshift = d0 < 8 ? 56 - 8 * d0 : 0;
+    __syncthreads();                           // s_hist is cleared (when no grid was built)
     // this workgroup's slice of the frame's peaks, in steps of BLOCK
     const int per = (np + gridDim.x - 1) / gridDim.x;
     const int k_lo = min(np, (int)blockIdx.x * per), k_hi = min(np, k_lo + per);
@@ -358,9 +369,14 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
         const int k = k0 + threadIdx.x;
         if (k < k_hi) {
             const GfttPeak p = J.peaks[k];
-            mine += (p.rbits > thr_bits && kept(p)) ? 1u : 0u;
+            if (p.rbits > thr_bits && kept(p)) {
+                mine += 1u;
+                if (d0 < 8) atomicAdd(&s_hist[(uint32_t)(p.rbits >> hshift) & 0xFFu], 1u);
+            }
         }
     }
+    __syncthreads();
+    if (d0 < 8 && s_hist[threadIdx.x]) atomicAdd(&J.hist[threadIdx.x], s_hist[threadIdx.x]);
     // wavefront and workgroup totals, one global atomic
     uint32_t wsum = mine;
 #pragma unroll
@@ -479,8 +495,8 @@ __device__ __forceinline__ uint32_t wave_append(bool take, uint32_t *ctr)
     return base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
 }
 
-__global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restrict__ jobs, int min_dist,
-                                                       int max_corners)
+__global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restrict__ jobs, double quality,
+                                                       int min_dist, int max_corners)
 {
     __shared__ SelSmem sm;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -492,6 +508,11 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     const bool spaced = min_dist >= 2;         // distinct pixels are always >= 1 apart
     const GfttPeak *cand = J.cand;
     const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
+    // every candidate's R bits lie in (thr_bits, max_bits] (the threshold is
+    // formed as the compaction forms it)
+    const unsigned long long max_bits = *J.max_bits;
+    const unsigned long long thr_bits =
+        (unsigned long long)__double_as_longlong(quality * __longlong_as_double((long long)max_bits));
 
     const OccGrid G = occ_grid_build<SBLOCK>(J, n_occ, min_dist, sm.grid);
     int remaining = np;
@@ -512,11 +533,22 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
         bool filtered = false;
         if (wn < remaining) {
             uint32_t need = (uint32_t)wn;
-            Key prefix{0, 0};
-            for (int d = 0; d < 12; ++d) {
+            // the eligible keys' R bits lie in (thr_bits, top]: their leading
+            // bytes are those thr_bits and top share, so the passes start
+            // after them
+            const unsigned long long top = bounded ? bound.hi : max_bits;
+            const unsigned long long diff = top ^ thr_bits;
+            const int d0 = diff ? (__clzll((long long)diff) >> 3) : 8;
+            Key prefix{d0 >= 8 ? top : (d0 == 0 ? 0ull : top & ~((1ull << (64 - 8 * d0)) - 1)), 0};
+            for (int d = d0; d < 12; ++d) {
                 for (int k = tid; k < (SBLOCK / 64) * 256; k += SBLOCK) (&sm.hist[0][0])[k] = 0;
                 __syncthreads();
-                for (int k0 = 0; k0 < nsrc; k0 += 8 * SBLOCK) {
+                // the first window's first digit: every candidate is eligible
+                // and carries the prefix, so the compaction's histogram is
+                // this pass's count
+                const bool counted = d == d0 && !bounded && d0 < 8;
+                if (counted && tid < 256) sm.hist[0][tid] = J.hist[tid];
+                for (int k0 = 0; k0 < (counted ? 0 : nsrc); k0 += 8 * SBLOCK) {
                     Key key[8];
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
@@ -683,64 +715,87 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                     blocked |= dd < md2d;
                 }
             }
-            sm.cx[tid] = x;
-            sm.cy[tid] = y;
-            __syncthreads();
-            // conflicts with better candidates of this chunk, 8 per step
-            unsigned long long m[CHUNK / 64];
-#pragma unroll
-            for (int w = 0; w < CHUNK / 64; ++w) m[w] = 0;
-            if (!blocked && spaced) {
-                const int4 *x4 = reinterpret_cast<const int4 *>(sm.cx), *y4 = reinterpret_cast<const int4 *>(sm.cy);
-                for (int u0 = 0; u0 < tid; u0 += 8) {
-                    const int4 xa = x4[u0 / 4], xb = x4[u0 / 4 + 1], ya = y4[u0 / 4], yb = y4[u0 / 4 + 1];
-                    const int ux[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-                    const int uy[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
-                    unsigned long long bits = 0;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const int dx = x - ux[i], dy = y - uy[i];
-                        bits |= (unsigned long long)((u0 + i < tid) && (dx * dx + dy * dy < md2)) << i;
-                    }
-#pragma unroll
-                    for (int w = 0; w < CHUNK / 64; ++w)
-                        if (w == (u0 >> 6)) m[w] |= bits << (u0 & 63);
-                }
-            }
-#pragma unroll
-            for (int w = 0; w < CHUNK / 64; ++w) sm.cmask[tid][w] = m[w];
+            // the candidates no taken corner or occupied point blocks, packed
+            // in rank order at cx / cy [0, mu)
             {
                 const unsigned long long free_bits = __ballot(!blocked);
                 if (lane == 0) sm.und[wv] = free_bits;
             }
             __syncthreads();
-            // wavefront 0 applies the greedy rule in rank order: candidate t
-            // (not blocked by earlier corners) is taken iff no taken
-            // candidate before it in the chunk conflicts with it
-            if (wv == 0 && !spaced) {
-                if (lane < CHUNK / 64) sm.sel[lane] = sm.und[lane];   // nothing conflicts
-            } else if (wv == 0) {
+            int mu = 0, at = 0;
+#pragma unroll
+            for (int w = 0; w < CHUNK / 64; ++w) {
+                const int c = __popcll(sm.und[w]);
+                mu += c;
+                at += w < wv ? c : 0;
+            }
+            at += __popcll(sm.und[wv] & ((1ull << lane) - 1));
+            if (!blocked) {
+                sm.cx[at] = x;
+                sm.cy[at] = y;
+            }
+            __syncthreads();
+            // packed candidate t = tid: its conflicts with the better packed
+            // candidates u < t (squared distance < min_dist^2), one 64-bit
+            // mask per group of 64, 8 tests per step
+            const bool live = tid < mu;
+            if (live && spaced) {
+                const int xt = sm.cx[tid], yt = sm.cy[tid];
+                const int4 *x4 = reinterpret_cast<const int4 *>(sm.cx), *y4 = reinterpret_cast<const int4 *>(sm.cy);
+#pragma unroll
+                for (int w = 0; w < CHUNK / 64; ++w) {
+                    if (64 * w > tid) break;
+                    unsigned long long mw = 0;
+                    const int u_end = min(tid, 64 * w + 64);
+                    for (int u0 = 64 * w; u0 < u_end; u0 += 8) {
+                        const int4 xa = x4[u0 / 4], xb = x4[u0 / 4 + 1], ya = y4[u0 / 4], yb = y4[u0 / 4 + 1];
+                        const int ux[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+                        const int uy[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
+                        unsigned long long bits = 0;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int dx = xt - ux[i], dy = yt - uy[i];
+                            bits |= (unsigned long long)((u0 + i < tid) && (dx * dx + dy * dy < md2)) << i;
+                        }
+                        mw |= bits << (u0 & 63);
+                    }
+                    sm.cmask[tid][w] = mw;
+                }
+            }
+            __syncthreads();
+            // wavefront 0 applies the greedy rule in rank order, a group of 64
+            // packed candidates at a time: a candidate is taken iff no taken
+            // better candidate conflicts with it.  Within a group the rule is
+            // resolved in rounds: an undecided candidate with a taken better
+            // conflict is rejected; one whose better conflicts are all decided
+            // and rejected is taken (the best undecided one always is, so
+            // every round decides at least one)
+            if (wv == 0) {
                 unsigned long long sel[CHUNK / 64];
 #pragma unroll
                 for (int g = 0; g < CHUNK / 64; ++g) {
-                    // lane = candidate 64 g + lane: conflicts with taken ones of earlier groups
+                    sel[g] = 0;
+                    if (64 * g >= mu) continue;
                     const int t = 64 * g + lane;
+                    const bool tl = t < mu;
                     bool hit = false;
+                    unsigned long long mg = 0;
+                    if (tl && spaced) {
 #pragma unroll
-                    for (int w = 0; w < CHUNK / 64; ++w)
-                        if (w < g) hit |= (sm.cmask[t][w] & sel[w]) != 0;
-                    const unsigned long long mg = sm.cmask[t][g];
-                    unsigned long long open = __ballot(!hit) & sm.und[g];
-                    unsigned long long s_g = 0;
-                    while (open) {
-                        const int b = __builtin_ctzll(open);
-                        open &= open - 1;
-                        const unsigned long long mb =
-                            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(mg >> 32), b) << 32)
-                            | (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mg, b);
-                        if ((mb & s_g) == 0) s_g |= 1ull << b;
+                        for (int w = 0; w < CHUNK / 64; ++w)
+                            if (w < g) hit |= (sm.cmask[t][w] & sel[w]) != 0;
+                        mg = sm.cmask[t][g];
                     }
-                    sel[g] = s_g;
+                    unsigned long long und = __ballot(tl && !hit), taken = 0;
+                    while (und) {
+                        const bool me = (und >> lane) & 1ull;
+                        const bool rej = me && (mg & taken) != 0;
+                        const bool tak = me && !rej && (mg & und) == 0;
+                        const unsigned long long bt = __ballot(tak), br = __ballot(rej);
+                        taken |= bt;
+                        und &= ~(bt | br);
+                    }
+                    sel[g] = taken;
                 }
                 if (lane == 0)
 #pragma unroll
@@ -756,9 +811,9 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 if (w < wv) before += __popcll(sw);
                 else if (w == wv) before += __popcll(sw & ((1ull << lane) - 1));
             }
-            const bool mine = (sm.sel[wv] >> lane) & 1ull;
+            const bool mine = live && ((sm.sel[wv] >> lane) & 1ull);
             const int pos = nt + before;
-            if (mine && pos < max_corners) sm.taken[pos] = (uint32_t)x | ((uint32_t)y << 16);
+            if (mine && pos < max_corners) sm.taken[pos] = (uint32_t)sm.cx[tid] | ((uint32_t)sm.cy[tid] << 16);
             nt = min(nt + total, max_corners);
             __syncthreads();
         }
@@ -776,13 +831,15 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     if (tid == 0) *J.count = nt;
 }
 
-__global__ void k_gftt_reset(const GfttJob *__restrict__ jobs, int njobs)
+// One workgroup of 256 threads per frame: counters, maximum, histogram.
+__global__ void k_gftt_reset(const GfttJob *__restrict__ jobs)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < njobs) {
-        *jobs[k].n_peaks = 0;
-        *jobs[k].n_cand = 0;
-        *jobs[k].max_bits = 0ull;
+    const GfttJob &J = jobs[blockIdx.x];
+    J.hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        *J.n_peaks = 0;
+        *J.n_cand = 0;
+        *J.max_bits = 0ull;
     }
 }
 
@@ -792,7 +849,7 @@ hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njo
                        int border, double quality, int min_dist, int max_corners, hipStream_t s)
 {
     if (njobs <= 0) return hipSuccess;
-    k_gftt_reset<<<(njobs + 255) / 256, 256, 0, s>>>(d_jobs, njobs);
+    k_gftt_reset<<<njobs, 256, 0, s>>>(d_jobs);
     switch (radius) {
     case 0: k_gftt_peaks<0><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     case 1: k_gftt_peaks<1><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
@@ -800,7 +857,7 @@ hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njo
     default: k_gftt_peaks<3><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     }
     k_gftt_compact<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality, min_dist);
-    k_gftt_select<<<njobs, SBLOCK, 0, s>>>(d_jobs, min_dist, max_corners);
+    k_gftt_select<<<njobs, SBLOCK, 0, s>>>(d_jobs, quality, min_dist, max_corners);
     return hipGetLastError();
 }
 

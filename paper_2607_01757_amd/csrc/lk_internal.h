@@ -112,6 +112,8 @@ struct GfttJob {
     GfttPeak *cand;                  // those above the quality threshold, capacity w * h
     int32_t *n_cand;
     unsigned long long *max_bits;    // bits of max(0, max R)
+    uint32_t *hist;                  // 256 bins: the candidates by the first byte of their R bits that the
+                                     // threshold and the maximum leave open (filled by the compaction)
     float *out_xy;
     int32_t *count;
     double *response;                // nullable
