@@ -419,6 +419,7 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
 // ---- selection --------------------------------------------------------------
 
 constexpr int CAPW = kGfttWindow;             // window of peaks sorted in LDS
+constexpr int TG_CELLS = 2048;                // cells of the taken-corner grid, at most
 constexpr int SBLOCK = 512;                   // threads of the selection workgroup
 constexpr int CHUNK = SBLOCK;                 // candidates decided together
 struct Key {
@@ -466,6 +467,8 @@ struct alignas(16) SelSmem {
     uint32_t taken[kGfttMaxCorners + 16];     // x | y << 16
     OccGridSmem grid;                          // the cached occupied points
     int32_t cx[CHUNK], cy[CHUNK];
+    int32_t tg_head[TG_CELLS];                 // taken corners by grid cell: first index, -1 for none
+    int32_t tg_next[kGfttMaxCorners + 16];     // the next index in the same cell
     uint32_t hist[SBLOCK / 64][256];           // one histogram per wavefront
     unsigned long long cmask[CHUNK][CHUNK / 64];   // conflicts with better candidates of the chunk
     unsigned long long sel[CHUNK / 64], und[CHUNK / 64];
@@ -478,6 +481,43 @@ struct alignas(16) SelSmem {
 __device__ __forceinline__ bool eligible(Key k, bool bounded, Key bound)
 {
     return !bounded || key_less(k, bound);
+}
+
+// The corners taken so far, grouped by the cells of a grid of cs x cs
+// pixels with cs >= min_dist (at most TG_CELLS cells), each cell a list
+// threaded through tg_next: a corner closer than min_dist to a pixel lies in
+// that pixel's cell or one of its 8 neighbours.
+struct TakenGrid {
+    int cs, gx, gy;
+};
+
+__device__ __forceinline__ TakenGrid taken_grid(int w, int h, int min_dist)
+{
+    TakenGrid T;
+    T.cs = min_dist > 1 ? min_dist : 1;
+    for (;;) {
+        T.gx = (w + T.cs - 1) / T.cs;
+        T.gy = (h + T.cs - 1) / T.cs;
+        if (T.gx * T.gy <= TG_CELLS) break;
+        T.cs += (T.cs >> 2) + 1;
+    }
+    return T;
+}
+
+// Some taken corner lies at squared distance < md2 from the in-frame pixel (x, y).
+__device__ __forceinline__ bool taken_blocked(const TakenGrid &T, const int32_t *head, const int32_t *next,
+                                              const uint32_t *taken, int x, int y, int md2)
+{
+    const int ccx = x / T.cs, ccy = y / T.cs;
+    bool blocked = false;
+    for (int yy = max(ccy - 1, 0); yy <= min(ccy + 1, T.gy - 1) && !blocked; ++yy)
+        for (int xx = max(ccx - 1, 0); xx <= min(ccx + 1, T.gx - 1) && !blocked; ++xx)
+            for (int q = head[yy * T.gx + xx]; q >= 0 && !blocked; q = next[q]) {
+                const uint32_t p = taken[q];
+                const int dx = x - (int)(p & 0xFFFFu), dy = y - (int)(p >> 16);
+                blocked = dx * dx + dy * dy < md2;
+            }
+    return blocked;
 }
 
 // Slot of this lane among the lanes of its wavefront that set `take`, in an
@@ -514,7 +554,9 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     const unsigned long long thr_bits =
         (unsigned long long)__double_as_longlong(quality * __longlong_as_double((long long)max_bits));
 
-    const OccGrid G = occ_grid_build<SBLOCK>(J, n_occ, min_dist, sm.grid);
+    const TakenGrid T = taken_grid(W, J.h, min_dist);
+    for (int c = tid; c < TG_CELLS; c += SBLOCK) sm.tg_head[c] = -1;
+    const OccGrid G = occ_grid_build<SBLOCK>(J, n_occ, min_dist, sm.grid);   // ends with a barrier
     int remaining = np;
     int nt = 0;
     bool bounded = false;
@@ -603,17 +645,22 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                     // the keys above the bucket and the bucket itself
                     if (tid == 0) sm.wcount = 0;
                     __syncthreads();
-                    for (int k0 = 0; k0 < nsrc; k0 += SBLOCK) {
-                        const int k = k0 + tid;
-                        GfttPeak p{};
-                        bool take = false;
-                        if (k < nsrc) {
-                            p = src[k];
-                            const Key key{p.rbits, ~p.idx};
-                            take = eligible(key, bounded, bound) && !key_less(key, prefix);
+                    // (8 keys per thread in flight, as in the counting passes)
+                    for (int k0 = 0; k0 < nsrc; k0 += 8 * SBLOCK) {
+                        GfttPeak p[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int k = k0 + i * SBLOCK + tid;
+                            p[i] = k < nsrc ? src[k] : GfttPeak{};
                         }
-                        const uint32_t at = wave_append(take, &sm.wcount);
-                        if (take) J.peaks[at] = p;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int k = k0 + i * SBLOCK + tid;
+                            const Key key{p[i].rbits, ~p[i].idx};
+                            const bool take = k < nsrc && eligible(key, bounded, bound) && !key_less(key, prefix);
+                            const uint32_t at = wave_append(take, &sm.wcount);
+                            if (take) J.peaks[at] = p[i];
+                        }
                     }
                     __syncthreads();             // the copy is visible to the whole workgroup
                     src = J.peaks;
@@ -624,9 +671,11 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             }
             low = prefix;
         }
-        // ---- gather the window and sort it (descending) in LDS
+        // ---- gather the window and sort it (descending) in LDS; keys a
+        // taken corner already blocks can never be taken and stay out
         if (tid == 0) sm.wcount = 0;
         __syncthreads();
+        const bool screen = spaced && nt > 0;
         for (int k0 = 0; k0 < nsrc; k0 += 8 * SBLOCK) {
             Key key[8];
 #pragma unroll
@@ -636,7 +685,11 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const bool take = key[i].hi != 0 && eligible(key[i], bounded, bound) && !key_less(key[i], low);
+                bool take = key[i].hi != 0 && eligible(key[i], bounded, bound) && !key_less(key[i], low);
+                if (take && screen) {
+                    const int idx = (int)~key[i].lo, yk = idx / W, xk = idx - yk * W;
+                    take = !taken_blocked(T, sm.tg_head, sm.tg_next, sm.taken, xk, yk, md2);
+                }
                 const uint32_t s = wave_append(take, &sm.wcount);
                 if (take && s < (uint32_t)CAPW) {
                     sm.whi[s] = key[i].hi;
@@ -645,9 +698,10 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             }
         }
         __syncthreads();
+        const int wu = min((int)sm.wcount, CAPW);   // the window's keys no taken corner blocks
         int pw = 1;
-        while (pw < wn) pw <<= 1;
-        for (int k = wn + tid; k < pw; k += SBLOCK) { sm.whi[k] = 0; sm.wlo[k] = 0; }
+        while (pw < wu) pw <<= 1;
+        for (int k = wu + tid; k < pw; k += SBLOCK) { sm.whi[k] = 0; sm.wlo[k] = 0; }
         __syncthreads();
         constexpr int PAIRS = CAPW / 2 / SBLOCK;
         for (int size = 2; size <= pw; size <<= 1) {
@@ -675,9 +729,9 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             }
         }
         // ---- accept in rank order, CHUNK candidates at a time
-        for (int c0 = 0; c0 < wn && nt < max_corners; c0 += CHUNK) {
+        for (int c0 = 0; c0 < wu && nt < max_corners; c0 += CHUNK) {
             const int k = c0 + tid;
-            const bool valid = k < wn;
+            const bool valid = k < wu;
             int x = 0, y = 0;
             bool blocked = !valid;
             if (valid) {
@@ -685,23 +739,9 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 y = idx / W;
                 x = idx - y * W;
             }
-            // corners taken so far, 16 per step
-            if (spaced && valid) {
-                const uint4 *t4 = reinterpret_cast<const uint4 *>(sm.taken);
-                for (int q = 0; q < nt && !blocked; q += 16) {
-                    uint32_t p[16];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const uint4 u = t4[q / 4 + v];
-                        p[4 * v] = u.x; p[4 * v + 1] = u.y; p[4 * v + 2] = u.z; p[4 * v + 3] = u.w;
-                    }
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int dx = x - (int)(p[i] & 0xFFFFu), dy = y - (int)(p[i] >> 16);
-                        blocked |= (q + i < nt) && (dx * dx + dy * dy < md2);
-                    }
-                }
-            }
+            // corners taken so far (those of earlier chunks: the window
+            // holds none an earlier window's corners block)
+            if (spaced && valid && nt > 0) blocked = taken_blocked(T, sm.tg_head, sm.tg_next, sm.taken, x, y, md2);
             // occupied points (binary64 distance): the grid, then any beyond the cache
             if (valid && n_occ > 0) {
                 blocked = blocked || occ_grid_blocked(G, sm.grid, x, y, md2d);
@@ -813,13 +853,18 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             }
             const bool mine = live && ((sm.sel[wv] >> lane) & 1ull);
             const int pos = nt + before;
-            if (mine && pos < max_corners) sm.taken[pos] = (uint32_t)sm.cx[tid] | ((uint32_t)sm.cy[tid] << 16);
+            if (mine && pos < max_corners) {
+                const int xm = sm.cx[tid], ym = sm.cy[tid];
+                sm.taken[pos] = (uint32_t)xm | ((uint32_t)ym << 16);
+                // into its grid cell's list (corners of one cell may arrive together)
+                sm.tg_next[pos] = atomicExch(&sm.tg_head[(ym / T.cs) * T.gx + xm / T.cs], pos);
+            }
             nt = min(nt + total, max_corners);
             __syncthreads();
         }
         remaining -= wn;
         bounded = true;
-        bound = Key{sm.whi[wn - 1], sm.wlo[wn - 1]};
+        bound = low;                 // the window was every eligible key >= low
         __syncthreads();
     }
     // corners in order, written once
