@@ -53,14 +53,15 @@ def level_dims(w, h, levels):
 
 def footprint_bytes(pts, ends, w, h, levels, win, store_bytes, grad_bytes=0):
     """Unique bytes of the window footprints the tracker must read: template
-    windows (win+3)^2 around p / 2^l in the previous pyramid (plus its
-    gradient planes, grad_bytes per pixel, when they are stored) and target
-    windows (win+1)^2 covering start and end in the next one."""
+    windows (win+3)^2 around p / 2^l in the previous pyramid (plus the
+    gradient planes of levels >= 1, grad_bytes per pixel, when they are
+    stored) and target windows (win+1)^2 covering start and end in the next
+    one."""
     hw = (win - 1) // 2
     total = 0
     for l, (lw, lh) in enumerate(level_dims(w, h, levels)):
         for pts_l, ext in ((pts / 2 ** l, hw + 2), (None, hw + 1)):
-            s = (1 if l == 0 else store_bytes) + (grad_bytes if pts_l is not None else 0)
+            s = (1 if l == 0 else store_bytes) + (grad_bytes if pts_l is not None and l > 0 else 0)
             diff = np.zeros((lh + 1, lw + 1), np.int32)
             if pts_l is not None:
                 x0 = np.floor(pts_l[:, 0]) - ext + 1
@@ -353,8 +354,8 @@ def run_batched(args):
     b_frames = sum(s.width * s.height for s in streams)
     esz = 2 if f16 else 4
     b_levels = sum(esz * sum(w * h for (w, h) in level_dims(s.width, s.height, 3)[1:]) for s in streams)
-    if f16:   # binary16 gradient planes of every level (4 B per pixel)
-        b_levels += sum(4 * sum(w * h for (w, h) in level_dims(s.width, s.height, 3)) for s in streams)
+    if f16:   # binary16 gradient planes of levels >= 1 (4 B per pixel)
+        b_levels += sum(4 * sum(w * h for (w, h) in level_dims(s.width, s.height, 3)[1:]) for s in streams)
     b_windows = 0
     off = 0
     for s in streams:

@@ -73,9 +73,11 @@ typedef enum {
 /* Storage of pyramid levels >= 1 (level 0 is always the 8-bit frame). */
 enum {
     LK_STORAGE_F32 = 0,  /* float levels; gradients computed on the fly from the levels */
-    LK_STORAGE_F16 = 1   /* binary16 levels (round to nearest even) and binary16 gradient
-                            planes (Gx, Gy interleaved) for every level, built from the
-                            stored levels; tracker arithmetic stays float32 */
+    LK_STORAGE_F16 = 1   /* binary16 levels (round to nearest even) and binary16 gradients
+                            (Gx, Gy) of every level, built from the stored levels: stored
+                            as interleaved planes for levels >= 1; those of level 0 (exact
+                            on the 8-bit frame, then rounded) are formed where they are
+                            used, with the same bits; tracker arithmetic stays float32 */
 };
 
 /* Per-point status codes written to d_status (uint8). */
@@ -126,7 +128,7 @@ uint64_t lk_context_bytes_in_use(const lk_context *ctx);
 
 /* ---- pyramids (steps 1-2) -------------------------------------------------
  * lk_pyramid_create allocates the levels >= 1 of a w x h frame (and, for
- * LK_STORAGE_F16, the gradient planes) in one device allocation.  Level 0 is
+ * LK_STORAGE_F16, their gradient planes) in one device allocation.  Level 0 is
  * not copied: lk_build_pyramid records d_img (8-bit, row pitch in bytes,
  * pitch >= w) and reads it during the build and during every later
  * lk_track* that uses the pyramid, so the caller keeps that buffer valid and

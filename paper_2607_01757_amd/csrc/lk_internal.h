@@ -73,9 +73,9 @@ struct DownJob {
 struct Pyr12Job {
     const uint8_t *src;
     void *dst1, *dst2;
-    __half2 *g0, *g1;                 // binary16 storage: gradient planes of levels 0 and 1 (else null)
+    __half2 *g1;                      // binary16 storage: gradient plane of level 1 (else null)
     int32_t spitch, pitch1, pitch2;   // elements per row
-    int32_t gpitch0, gpitch1;         // half2 elements per row of g0, g1
+    int32_t gpitch1;                  // half2 elements per row of g1
     int32_t sw, sh, w1, h1, w2, h2;
     int32_t f16;                      // levels stored as binary16
     int32_t tiles_x, tile_begin;

@@ -235,10 +235,10 @@ __global__ __launch_bounds__(kThreads) void k_downsample_batched(const DownJob *
 // ------------------------------------------------ levels 1 and 2 in one pass
 //
 // Workgroup = one 32 x 16 tile of level 2 at (ox2, oy2).  Binary16 storage
-// also writes the gradient planes of levels 0 and 1 for the 128 x 64 and
-// 64 x 32 blocks under the tile, from the staged bytes and the level-1
-// region (both gradients are exact before the binary16 rounding, so they
-// carry the bits of the gradient-plane kernel).  Level 1 is formed
+// also writes the gradient plane of level 1 for the 64 x 32 tile under it,
+// from the level-1 region (exact before the binary16 rounding, so it carries
+// the bits of the gradient-plane kernel); level 0 has no stored plane (the
+// tracker forms its binary16 gradients from the 8-bit frame).  Level 1 is formed
 // on the region x1 in [2 ox2 - 2, 2 ox2 + 65), y1 in [2 oy2 - 2, 2 oy2 + 33)
 // (the 64 x 32 tile under the level-2 tile plus the two-pixel halo the
 // level-2 filter needs) from level 0 staged as bytes; the level-1 tile is
@@ -360,63 +360,6 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
                 sm.l1[r][c] = to_storage(v.x, f16);
                 sm.l1[r][c + 1] = to_storage(v.y, f16);
                 h0 = h2; h1 = h3; h2 = h4;
-            }
-        }
-    }
-    if constexpr (F16) {
-        // 2b. level-0 gradient plane of the 128 x 64 block at (4 ox2, 4 oy2):
-        //     thread = 4 columns x 8 rows; per staged row, the central
-        //     differences d and the [3 10 3] sums s of its 4 pixels (integers,
-        //     from the 6 bytes around them), slid down the rows:
-        //     Gx = (3 (d[-1] + d[+1]) + 10 d[0]) / 32, Gy = (s[+1] - s[-1]) / 32
-        const int c = 4 * (threadIdx.x & 31), r0 = 8 * (threadIdx.x >> 5);
-        const int x = 4 * ox2 + c, y0 = 4 * oy2 + r0;
-        // staged column of level-0 x is c + 16, staged row of y0 + k is r0 + 6 + k
-        auto row = [&](int k, int (&d)[4], int (&sr)[4]) {
-            const uint32_t *q = reinterpret_cast<const uint32_t *>(&sm.in[r0 + 6 + k][c + 12]);
-            const uint32_t wm = q[0], w0 = q[1], wp = q[2];
-            int p6[6];
-            p6[0] = (int)(wm >> 24);
-#pragma unroll
-            for (int m = 0; m < 4; ++m) p6[m + 1] = (int)((w0 >> (8 * m)) & 0xFFu);
-            p6[5] = (int)(wp & 0xFFu);
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                d[m] = p6[m + 2] - p6[m];
-                sr[m] = 3 * (p6[m] + p6[m + 2]) + 10 * p6[m + 1];
-            }
-        };
-        int dA[4], sA[4], dB[4], sB[4];
-        row(-1, dA, sA);
-        row(0, dB, sB);
-        for (int k = 0; k < 8; ++k) {
-            int dC[4], sC[4];
-            row(k + 1, dC, sC);
-            const int y = y0 + k;
-            if (y < j.sh && x < j.sw) {
-                __half2 g[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    g[m] = __floats2half2_rn((float)(3 * (dA[m] + dC[m]) + 10 * dB[m]) * 0.03125f,
-                                             (float)(sC[m] - sA[m]) * 0.03125f);
-                __half2 *dst = j.g0 + (size_t)y * j.gpitch0 + x;
-                if (x + 3 < j.sw) {
-                    uint4 u;
-                    u.x = __builtin_bit_cast(uint32_t, g[0]);
-                    u.y = __builtin_bit_cast(uint32_t, g[1]);
-                    u.z = __builtin_bit_cast(uint32_t, g[2]);
-                    u.w = __builtin_bit_cast(uint32_t, g[3]);
-                    *reinterpret_cast<uint4 *>(dst) = u;
-                } else {
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        if (x + m < j.sw) dst[m] = g[m];
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                dA[m] = dB[m]; sA[m] = sB[m];
-                dB[m] = dC[m]; sB[m] = sC[m];
             }
         }
     }
@@ -902,6 +845,9 @@ __device__ __forceinline__ float bilerp(const Weights &w, float a, float b, floa
 __device__ __forceinline__ float lerp_row(float ax, float left, float diff) { return fmaf(ax, diff, left); }
 __device__ __forceinline__ float lerp_col(float ay, float top, float bottom) { return fmaf(ay, bottom - top, top); }
 
+// Binary16 rounding of a float (round to nearest even), returned as float.
+__device__ __forceinline__ float round_f16(float v) { return __half2float(__float2half_rn(v)); }
+
 // Template data of level l in LDS.  E (SW x SH): the level region from
 // (tx_lo, ty_lo) with a one-pixel halo around the tap positions; GX, GY
 // (TW x TH): Scharr gradients at tap positions (tx_lo + 1 + tc, ty_lo + 1 +
@@ -912,9 +858,11 @@ __device__ __forceinline__ float lerp_col(float ay, float top, float bottom) { r
 //
 // Float levels: E is staged with coalesced loads (reflect-101 applied to the
 // addresses near an edge), then each lane walks one tap column down E with a
-// three-row window and writes the gradients.  Binary16 levels: the value and
+// three-row window and writes the gradients (R16: rounded to binary16, the
+// level-0 gradients of binary16 storage, which are formed here, exactly on
+// the 8-bit frame, instead of stored).  Binary16 levels >= 1: the value and
 // the stored gradients are read at the clamped tap positions.
-template <class G, int KIND, bool PLANES>
+template <class G, int KIND, bool PLANES, bool R16 = false>
 __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty_lo, int lane, float *lds)
 {
     float *E = lds, *TX = lds + G::SW * G::SH, *TY = TX + G::TW * G::TH;
@@ -972,8 +920,9 @@ __device__ __forceinline__ void stage_taps(const LevelDesc &L, int tx_lo, int ty
                 const float a = ok ? e[0] : 0.0f, b = ok ? e[1] : 0.0f, c = ok ? e[2] : 0.0f;
                 const float d2 = c - a, s2 = fmaf(3.0f, a + c, 10.0f * b);
                 if (ok) {
-                    TX[tr * G::TW + tc] = (3.0f * d0 + 10.0f * d1 + 3.0f * d2) * 0.03125f;
-                    TY[tr * G::TW + tc] = (s2 - s0) * 0.03125f;
+                    const float gx = (3.0f * d0 + 10.0f * d1 + 3.0f * d2) * 0.03125f, gy = (s2 - s0) * 0.03125f;
+                    TX[tr * G::TW + tc] = R16 ? round_f16(gx) : gx;
+                    TY[tr * G::TW + tc] = R16 ? round_f16(gy) : gy;
                 }
                 d0 = d1; d1 = d2; s0 = s1; s1 = s2;
             }
@@ -1322,6 +1271,70 @@ __device__ __forceinline__ void fast_template_planes(const Plane &P, const Level
     }
 }
 
+// Template of a level-0 window whose taps lie inside the frame, binary16
+// storage (one column per lane): the binary16 (Gx, Gy) of level 0 are not
+// stored; each lane forms those of its taps from the 8-bit frame instead.
+// Per frame row by-1 .. by+R+1 it loads the four bytes at columns bx-1 ..
+// bx+2 (one 8-byte load from the 4-byte-aligned offset at or below them),
+// forms the central differences and [3 10 3] sums of its two tap columns,
+// and per tap row the Scharr gradients, exact on 8-bit data, then rounds
+// them to binary16: the values a stored plane would hold.  T, Gx and Gy are
+// sampled in the lerp form the target samples use.  (bx, by): the lane's
+// first tap; the caller keeps rows by-1 .. by+R+1 and columns bx-1 .. bx+2
+// inside the frame and off its last row (the 8-byte loads read up to 4
+// bytes past column bx+2).  An idle lane of an exact build reads beyond the
+// buffer (zeros), so its T, Gx and Gy are zero.
+template <class G>
+__device__ __forceinline__ void fast_template_u8_r16(const Plane &P, int bx, int by, float ax, float ay,
+                                                     const LaneCfg &lc, int win, float (&T)[G::R][G::CW],
+                                                     float (&GX)[G::R][G::CW], float (&GY)[G::R][G::CW])
+{
+    static_assert(G::CW == 1, "one window column per lane");
+    constexpr int R = G::R;
+    constexpr int kFar = 0x40000000;       // beyond every frame
+    const bool live = !G::EXACT || lc.active;
+    const int voff = live ? (by - 1) * P.pitch + bx - 1 : kFar;
+    // every row's load first (one wait), then the rows in order with a
+    // three-row window of differences and sums
+    uint32_t lo[R + 3], hi[R + 3];
+#pragma unroll
+    for (int k = 0; k < R + 3; ++k) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(P.rs, (voff + k * P.pitch) & ~3, 0, 0);
+        lo[k] = v[0]; hi[k] = v[1];    // (copied out: see fast_template_planes)
+    }
+    float dl0 = 0.0f, dr0 = 0.0f, sl0 = 0.0f, sr0 = 0.0f, dl1 = 0.0f, dr1 = 0.0f, sl1 = 0.0f, sr1 = 0.0f;
+    float tl1 = 0.0f, tr1 = 0.0f, e0 = 0.0f, x0 = 0.0f, y0 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < R + 3; ++k) {
+        const uint32_t w = __builtin_amdgcn_alignbit(hi[k], lo[k], (uint32_t)((voff + k * P.pitch) & 3) * 8u);
+        const float q0 = (float)(w & 0xFFu), q1 = (float)((w >> 8) & 0xFFu);
+        const float q2 = (float)((w >> 16) & 0xFFu), q3 = (float)(w >> 24);
+        const float dl2 = q2 - q0, dr2 = q3 - q1;
+        const float sl2 = fmaf(3.0f, q0 + q2, 10.0f * q1), sr2 = fmaf(3.0f, q1 + q3, 10.0f * q2);
+        if (k >= 2) {
+            // tap row i = k - 2 (frame row by + i, the middle of the window)
+            const int i = k - 2;
+            const float gxl = round_f16(fmaf(3.0f, dl0 + dl2, 10.0f * dl1) * 0.03125f);
+            const float gxr = round_f16(fmaf(3.0f, dr0 + dr2, 10.0f * dr1) * 0.03125f);
+            const float gyl = round_f16((sl2 - sl0) * 0.03125f);
+            const float gyr = round_f16((sr2 - sr0) * 0.03125f);
+            const float e1 = lerp_row(ax, tl1, tr1 - tl1);
+            const float x1 = lerp_row(ax, gxl, gxr - gxl);
+            const float y1 = lerp_row(ax, gyl, gyr - gyl);
+            if (i >= 1) {
+                const bool ok = g_valid<G>(lc, win, i - 1, 0);
+                T[i - 1][0] = lerp_col(ay, e0, e1);      // invalid pixels have GX = GY = 0: they add nothing
+                GX[i - 1][0] = ok ? lerp_col(ay, x0, x1) : 0.0f;
+                GY[i - 1][0] = ok ? lerp_col(ay, y0, y1) : 0.0f;
+            }
+            e0 = e1; x0 = x1; y0 = y1;
+        }
+        dl0 = dl1; dr0 = dr1; sl0 = sl1; sr0 = sr1;
+        dl1 = dl2; dr1 = dr2; sl1 = sl2; sr1 = sr2;
+        tl1 = q1; tr1 = q2;
+    }
+}
+
 struct PassResult {
     int status;
     float ox, oy;      // end point, level-0 pixels
@@ -1404,15 +1417,20 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
                 fast = tx_lo >= 0 && ty_lo >= 0 && tx_lo + G::SW <= LI.w && ty_lo + G::SH <= LI.h;
             if constexpr (ST == LK_STORAGE_F16 && G::CW == 1) {
                 // every lane's taps (columns cix - h .. cix - h + EXX, rows
-                // likewise) inside the level
-                fast = cix - h >= 0 && ciy - h >= 0 && cix - h + G::EXX < LI.w && ciy - h + G::EXY < LI.h - 1;
+                // likewise) inside the level and off its last row; at level 0
+                // also the one-pixel ring its gradients are formed from
+                if (l == 0)
+                    fast = cix - h - 1 >= 0 && ciy - h - 1 >= 0 && cix - h + G::EXX + 1 < LI.w &&
+                           ciy - h + G::EXY + 1 < LI.h - 1;
+                else
+                    fast = cix - h >= 0 && ciy - h >= 0 && cix - h + G::EXX < LI.w && ciy - h + G::EXY < LI.h - 1;
             }
             if (fast) {
                 if constexpr (ST == LK_STORAGE_F16 && G::CW == 1) {
                     const int bx = cix - h + lc.c0, by = ciy - h + lc.r0;
                     if (l == 0)
-                        fast_template_planes<G, K_U8>(make_plane<K_U8>(LI.img, LI.pitch, LI.w, LI.h), LI, bx, by, cfx,
-                                                      cfy, lc, win, T, GX, GY);
+                        fast_template_u8_r16<G>(make_plane<K_U8>(LI.img, LI.pitch, LI.w, LI.h), bx, by, cfx, cfy, lc,
+                                                win, T, GX, GY);
                     else
                         fast_template_planes<G, K_F16>(make_plane<K_F16>(LI.img, LI.pitch, LI.w, LI.h), LI, bx, by,
                                                        cfx, cfy, lc, win, T, GX, GY);
@@ -1426,7 +1444,7 @@ __device__ PassResult run_pass(const PyrDesc &I, const PyrDesc &J, float px, flo
                                                 cfy, lc, win, lane, lds, T, GX, GY);
                 }
             } else {
-                if (l == 0) stage_taps<G, K_U8, ST == LK_STORAGE_F16>(LI, tx_lo, ty_lo, lane, lds);
+                if (l == 0) stage_taps<G, K_U8, false, ST == LK_STORAGE_F16>(LI, tx_lo, ty_lo, lane, lds);
                 else if constexpr (ST == LK_STORAGE_F16) stage_taps<G, K_F16, true>(LI, tx_lo, ty_lo, lane, lds);
                 else stage_taps<G, K_F32, false>(LI, tx_lo, ty_lo, lane, lds);
                 lane_template<G>(lds, lc, win, bilinear_weights(cfx, cfy), cfx, cfy, cix - h + lc.c0, ciy - h + lc.r0,
@@ -1766,7 +1784,10 @@ __global__ void k_write_descs(const PyrDescWrite *w, int n)
 
 // One level (and its gradient plane) as float, for diagnostics; kind: the
 // element type of the level (level 0 is 8-bit).
-__global__ __launch_bounds__(kThreads) void k_read_level(LevelDesc lv, int kind, float *dst, float *dgrad)
+// grad_u8: the binary16 gradients of an 8-bit level (binary16 storage, level
+// 0, which has no stored plane), formed as the tracker forms them.
+__global__ __launch_bounds__(kThreads) void k_read_level(LevelDesc lv, int kind, int grad_u8, float *dst,
+                                                         float *dgrad)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= lv.w * lv.h) return;
@@ -1774,7 +1795,18 @@ __global__ __launch_bounds__(kThreads) void k_read_level(LevelDesc lv, int kind,
     dst[i] = kind == K_U8    ? ldpx<K_U8>(lv.img, y * lv.pitch + x)
              : kind == K_F16 ? ldpx<K_F16>(lv.img, y * lv.pitch + x)
                              : ldpx<K_F32>(lv.img, y * lv.pitch + x);
-    if (dgrad && lv.grad) {
+    if (dgrad && grad_u8) {
+        // Scharr on the frame with reflect-101 borders, exact, then rounded
+        auto px = [&](int yy, int xx) {
+            return ldpx<K_U8>(lv.img, reflect101(yy, lv.h) * lv.pitch + reflect101(xx, lv.w));
+        };
+        const float dA = px(y - 1, x + 1) - px(y - 1, x - 1), dB = px(y, x + 1) - px(y, x - 1);
+        const float dC = px(y + 1, x + 1) - px(y + 1, x - 1);
+        const float sA = fmaf(3.0f, px(y - 1, x - 1) + px(y - 1, x + 1), 10.0f * px(y - 1, x));
+        const float sC = fmaf(3.0f, px(y + 1, x - 1) + px(y + 1, x + 1), 10.0f * px(y + 1, x));
+        dgrad[2 * i] = round_f16(fmaf(3.0f, dA + dC, 10.0f * dB) * 0.03125f);
+        dgrad[2 * i + 1] = round_f16((sC - sA) * 0.03125f);
+    } else if (dgrad && lv.grad) {
         const float2 g = __half22float2(lv.grad[y * lv.gpitch + x]);
         dgrad[2 * i] = g.x;
         dgrad[2 * i + 1] = g.y;
@@ -1976,8 +2008,9 @@ hipError_t launch_read_level(const LevelDesc &lv, int level, int storage, float 
 {
     const int kind = level == 0 ? K_U8 : (storage == LK_STORAGE_F16 ? K_F16 : K_F32);
     const long n = (long)lv.w * lv.h;
+    const int grad_u8 = level == 0 && storage == LK_STORAGE_F16;
     hipLaunchKernelGGL(k_read_level, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, stream,
-                       lv, kind, dst, dgrad);
+                       lv, kind, grad_u8, dst, dgrad);
     return hipGetLastError();
 }
 

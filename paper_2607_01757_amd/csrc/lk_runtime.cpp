@@ -165,8 +165,7 @@ void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<D
         j.spitch = d.lv[0].pitch; j.pitch1 = d.lv[1].pitch; j.pitch2 = d.lv[2].pitch;
         j.sw = d.lv[0].w; j.sh = d.lv[0].h; j.w1 = d.lv[1].w; j.h1 = d.lv[1].h; j.w2 = d.lv[2].w; j.h2 = d.lv[2].h;
         j.f16 = f16;
-        if (f16) {      // the fused launch also writes the gradient planes of levels 0 and 1
-            j.g0 = const_cast<__half2 *>(d.lv[0].grad); j.gpitch0 = d.lv[0].gpitch;
+        if (f16) {      // the fused launch also writes the gradient plane of level 1
             j.g1 = const_cast<__half2 *>(d.lv[1].grad); j.gpitch1 = d.lv[1].gpitch;
         }
         j.tiles_x = (j.w2 + kP12TileW - 1) / kP12TileW;
@@ -184,8 +183,8 @@ void pyramid_jobs(const lk_pyramid *p, std::vector<Pyr12Job> *p12, std::vector<D
         j.tile_begin = 0;
         down_by_level[l].push_back(j);
     }
-    if (f16)
-        for (int l = first == 3 ? 2 : 0; l < d.levels; ++l) {
+    if (f16)   // level 0 has no stored plane: the tracker forms its gradients from the frame
+        for (int l = first == 3 ? 2 : 1; l < d.levels; ++l) {
             GradJob g{};
             g.src = d.lv[l].img; g.dst = const_cast<__half2 *>(d.lv[l].grad);
             g.spitch = d.lv[l].pitch; g.dpitch = d.lv[l].gpitch;
@@ -295,7 +294,7 @@ lk_result lk_pyramid_create(lk_context *ctx, int32_t w, int32_t h, int32_t level
             off[l] = total;
             total = align_up(total + (size_t)d.lv[l].pitch * hs[l] * es, 256);
         }
-        if (storage == LK_STORAGE_F16) {
+        if (storage == LK_STORAGE_F16 && l > 0) {
             d.lv[l].gpitch = (int32_t)align_up(ws[l], 64);
             goff[l] = total;
             total = align_up(total + (size_t)d.lv[l].gpitch * hs[l] * 4, 256);
@@ -316,7 +315,7 @@ lk_result lk_pyramid_create(lk_context *ctx, int32_t w, int32_t h, int32_t level
     p->d_desc = reinterpret_cast<PyrDesc *>(b);
     for (int l = 0; l < levels; ++l) {
         if (l > 0) d.lv[l].img = b + off[l];
-        if (storage == LK_STORAGE_F16) d.lv[l].grad = reinterpret_cast<const __half2 *>(b + goff[l]);
+        if (storage == LK_STORAGE_F16 && l > 0) d.lv[l].grad = reinterpret_cast<const __half2 *>(b + goff[l]);
     }
     *out = p;
     return LK_SUCCESS;
