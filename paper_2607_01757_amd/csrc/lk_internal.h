@@ -186,7 +186,8 @@ hipError_t launch_downsample(const DownJob &job, hipStream_t stream);
 // d_tile_job[t].
 hipError_t launch_downsample_batched(const DownJob *d_jobs, const int32_t *d_tile_job, int total_tiles,
                                      hipStream_t stream);
-hipError_t launch_pyr12(const Pyr12Job &job, hipStream_t stream);
+// ddst (nullable): also writes the pyramid's device descriptor (desc).
+hipError_t launch_pyr12(const Pyr12Job &job, PyrDesc *ddst, const PyrDesc &desc, hipStream_t stream);
 // d_descs / n_descs: descriptor writes folded into the launch (one per
 // workgroup, n_descs <= total_tiles), or nullptr / 0
 hipError_t launch_pyr12_batched(const Pyr12Job *d_jobs, const int32_t *d_tile_job, int total_tiles,

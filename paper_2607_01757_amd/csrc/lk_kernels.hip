@@ -497,9 +497,13 @@ __device__ void pyr12_tile(const Pyr12Job &j, int tile, P12Smem &sm)
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_pyr12(Pyr12Job j)
+// ddst (nullable): the pyramid's device descriptor, written with desc by one
+// thread of workgroup 0 (only launches after this one read it), which saves
+// the descriptor-write launch of a build.
+__global__ __launch_bounds__(kThreads) void k_pyr12(Pyr12Job j, PyrDesc *ddst, PyrDesc desc)
 {
     __shared__ P12Smem sm;
+    if (ddst && blockIdx.x == 0 && threadIdx.x == 0) *ddst = desc;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     if (j.f16) pyr12_tile<true>(j, tile, sm);
     else pyr12_tile<false>(j, tile, sm);
@@ -1896,10 +1900,10 @@ hipError_t launch_downsample_batched(const DownJob *d_jobs, const int32_t *d_til
     return hipGetLastError();
 }
 
-hipError_t launch_pyr12(const Pyr12Job &job, hipStream_t stream)
+hipError_t launch_pyr12(const Pyr12Job &job, PyrDesc *ddst, const PyrDesc &desc, hipStream_t stream)
 {
     const int tiles = job.tiles_x * ((job.h2 + kP12TileH - 1) / kP12TileH);
-    hipLaunchKernelGGL(k_pyr12, dim3(tiles), dim3(kThreads), 0, stream, job);
+    hipLaunchKernelGGL(k_pyr12, dim3(tiles), dim3(kThreads), 0, stream, job, ddst, desc);
     return hipGetLastError();
 }
 

@@ -359,12 +359,14 @@ lk_result lk_build_pyramid(lk_context *ctx, lk_pyramid *pyr, const uint8_t *d_im
     std::vector<DownJob> down[LK_MAX_LEVELS];
     std::vector<GradJob> grads;
     pyramid_jobs(pyr, &p12, down, &grads);
-    {
+    // the device descriptor rides on the fused level-1/2 launch when there is
+    // one (a pyramid of three or more levels), else it takes a launch of its own
+    if (p12.empty()) {
         hipError_t e = launch_write_desc(pyr->d_desc, pyr->desc, s);
         if (e != hipSuccess) return hip_fail(e, "descriptor write launch");
     }
-    for (auto &j : p12) {
-        hipError_t e = launch_pyr12(j, s);
+    for (size_t i = 0; i < p12.size(); ++i) {
+        hipError_t e = launch_pyr12(p12[i], i == 0 ? pyr->d_desc : nullptr, pyr->desc, s);
         if (e != hipSuccess) return hip_fail(e, "pyramid kernel launch");
     }
     for (int l = 1; l < pyr->desc.levels; ++l)

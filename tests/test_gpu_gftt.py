@@ -103,6 +103,24 @@ def test_many_windows_large_frame(det):
     assert np.array_equal(got, want)
 
 
+def test_candidates_exhausted_before_max_corners(det):
+    # the frame cannot hold max_corners corners min_dist apart: every window
+    # of candidates is gathered and decided, most of them already blocked by
+    # corners of earlier windows (the case of a top-up beside many tracked
+    # points); with and without occupied points, and a small min_dist whose
+    # taken-corner grid needs cells larger than min_dist
+    im = texture(480, 752, 11)
+    rng = np.random.default_rng(4)
+    occ = np.column_stack([rng.uniform(0, 752, 200), rng.uniform(0, 480, 200)]).astype(np.float32)
+    for kw, o in ((dict(r=1, quality=0.001, min_dist=30, max_corners=4096), None),
+                  (dict(r=1, quality=0.001, min_dist=30, max_corners=4096), occ),
+                  (dict(r=1, quality=0.005, min_dist=3, max_corners=4096), occ)):
+        (got, _), = run(det, [im], occupied=[o], **kw)
+        want = oracle_corners(im, occ=o, **kw)
+        assert len(want) < kw["max_corners"]
+        assert np.array_equal(got, want), (kw, o is None)
+
+
 def test_ties_and_plateaus(det):
     # a periodic pattern gives many exactly equal responses: ties are broken
     # by raster index, plateaus of equal maxima are all candidates
