@@ -866,8 +866,13 @@ def run_detect(args):
         assert np.array_equal(got, want), "detector differs from the oracle on frame %d" % i
     # algorithmic operations per pixel (radius 1): Scharr pair 16, tensor
     # products 3, separable 3x3 sums 12, two integer tensor combinations 2,
-    # NMS 8 compares (41 full-rate ops) + 10 binary64 ops at half rate
-    ops = px * (41 + 2 * 10)
+    # NMS 8 compares (41 integer ops) + 10 binary64 ops (3 conversions, 3
+    # products, a sum, the square root, a difference, a halving).  CDNA4
+    # issues a binary64 VALU op at the rate of an int32 one: one op per lane
+    # per clock, 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
+    # (the fp32 vector peak / 4: no FMA pairs, no packed pairs)
+    ops = px * (41 + 10)
+    peak_lane_ops = PEAK_FP32_TFLOPS / 4
     t = res["fresh"]["ms_per_step"] * 1e-3
     result = {
         "metric": "corner detection frames/sec (batched, 64 streams)", "value": res["fresh"]["frames_per_s"],
@@ -878,9 +883,9 @@ def run_detect(args):
                                "3x3 block, quality 0.01, min distance 30, up to %d corners per frame" % cap,
                    "streams": len(streams), "pixels_per_step": px},
         "topup": res["topup"], "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
-        "roofline": {"bound": "alu", "kernel": "k_gftt_peaks+k_gftt_select", "achieved": ops / t / 1e12,
-                     "peak": PEAK_FP32_TFLOPS / 2, "unit": "Tops/s (full-rate VALU lane ops)",
-                     "frac": ops / t / 1e12 / (PEAK_FP32_TFLOPS / 2), "traffic": None},
+        "roofline": {"bound": "alu", "kernel": "detection step (reset, peaks, compaction, buckets, selection)",
+                     "achieved": ops / t / 1e12, "peak": peak_lane_ops, "unit": "T VALU lane-ops/s",
+                     "frac": ops / t / 1e12 / peak_lane_ops, "traffic": None},
     }
     if not args.no_cpu_baseline:
         sample = streams[:8]

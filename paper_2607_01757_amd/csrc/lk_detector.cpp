@@ -18,7 +18,7 @@ struct lk_detector {
     size_t bytes = 0;
     int32_t *d_counts = nullptr;     // n_peaks of frame f at [2 f], n_cand at [2 f + 1]
     unsigned long long *d_max = nullptr;
-    uint32_t *d_hist = nullptr;      // 256 bins per frame
+    uint32_t *d_hist = nullptr;      // 256 bins, then 256 bucket counters, per frame
     GfttPeak *d_peaks = nullptr;
     GfttPeak *d_cand = nullptr;
 };
@@ -47,21 +47,24 @@ lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const l
     if (n_frames == 0) return LK_SUCCESS;
     int64_t pixels = 0;
     long long tiles = 0;
+    int tw = 0, th = 0;
+    gftt_tile_shape(p->radius, &tw, &th);
     for (int f = 0; f < n_frames; ++f) {
         GfttJob &J = jobs[f];
         if (J.w < 3 || J.h < 3 || J.w > 32768 || J.h > 32768)
             return fail(LK_ERR_INVALID_ARG, "frame %d: size %dx%d not in [3, 32768]^2", f, J.w, J.h);
         if (J.pitch < J.w) return fail(LK_ERR_INVALID_ARG, "frame %d: pitch < width", f);
-        J.tiles_x = (J.w + kGfttTileW - 1) / kGfttTileW;
+        J.tiles_x = (J.w + tw - 1) / tw;
         J.tile_begin = (int32_t)tiles;
         J.peaks = det->d_peaks + pixels;
         J.n_peaks = det->d_counts + 2 * f;
         J.cand = det->d_cand + pixels;
         J.n_cand = det->d_counts + 2 * f + 1;
         J.max_bits = det->d_max + f;
-        J.hist = det->d_hist + 256 * (size_t)f;
+        J.hist = det->d_hist + 512 * (size_t)f;
+        J.cursor = J.hist + 256;
         pixels += (int64_t)J.w * J.h;
-        tiles += (long long)J.tiles_x * ((J.h + kGfttTileH - 1) / kGfttTileH);
+        tiles += (long long)J.tiles_x * ((J.h + th - 1) / th);
     }
     if (pixels > det->max_pixels)
         return fail(LK_ERR_INVALID_ARG, "%lld pixels exceed the detector's %lld", (long long)pixels,
@@ -71,7 +74,7 @@ lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const l
     // jobs, then the job of every tile
     std::vector<int32_t> tile_job((size_t)tiles);
     for (int f = 0; f < n_frames; ++f) {
-        const long long n = (long long)jobs[f].tiles_x * ((jobs[f].h + kGfttTileH - 1) / kGfttTileH);
+        const long long n = (long long)jobs[f].tiles_x * ((jobs[f].h + th - 1) / th);
         std::fill(tile_job.begin() + jobs[f].tile_begin, tile_job.begin() + jobs[f].tile_begin + n, f);
     }
     StagingRing::Slot *slot = nullptr;
@@ -104,7 +107,7 @@ lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pi
     const size_t max_off = cnt_bytes;
     const size_t max_bytes = ((size_t)max_frames * sizeof(unsigned long long) + 255) & ~size_t(255);
     const size_t hist_off = max_off + max_bytes;
-    const size_t hist_bytes = (size_t)max_frames * 256 * sizeof(uint32_t);
+    const size_t hist_bytes = (size_t)max_frames * 512 * sizeof(uint32_t);
     const size_t peaks_off = hist_off + hist_bytes;
     const size_t cand_off = peaks_off + (size_t)max_pixels * sizeof(GfttPeak);
     const size_t bytes = cand_off + (size_t)max_pixels * sizeof(GfttPeak);

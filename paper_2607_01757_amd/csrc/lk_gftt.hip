@@ -5,24 +5,27 @@
 // quality threshold, greedy minimum-distance selection in rank order) is the
 // one stated in lk.h; results are exact, not approximations of it.
 //
-// Four launches per call, all frames of the call at once:
-//   k_gftt_reset   zero the per-frame peak counters and maxima (a fill kernel,
-//                  safe under graph capture);
-//   k_gftt_peaks   one 64x16 tile per workgroup: the frame window with a halo
-//                  is staged in LDS, gradients, block sums and the response
-//                  are formed there, every in-frame 3x3 local maximum with
-//                  R > 0 is appended to the frame's peak list and the frame
-//                  maximum is raised with one atomic per workgroup;
+// Five launches per call, all frames of the call at once:
+//   k_gftt_reset   zero the per-frame peak counters, maxima and bucket
+//                  counters (a fill kernel, safe under graph capture);
+//   k_gftt_peaks   the response, its 3x3 local maxima with R > 0 appended to
+//                  the frame's peak list, the frame maximum raised with one
+//                  atomic per workgroup: block radius 0 and 1 walk 60x64
+//                  strips with one wavefront each (k_gftt_peaks_strip), radius
+//                  2 and 3 stage 64x16 tiles in LDS;
 //   k_gftt_compact keeps the peaks above the quality threshold that no cached
-//                  occupied point blocks;
-//   k_gftt_select  one workgroup per frame: the quality threshold follows
-//                  from the maximum; windows of the best remaining peaks are
-//                  found by radix selection on the 96-bit rank key (R bits,
-//                  then the complemented raster index), sorted in LDS, and
-//                  accepted 512 at a time against the corners taken so far
-//                  and the occupied points.  The acceptance within a chunk
-//                  resolves the greedy rule exactly (a candidate is taken
-//                  iff no better candidate that is taken lies too close).
+//                  occupied point blocks and counts them by bucket (the first
+//                  byte of their R bits that the threshold leaves open);
+//   k_gftt_bucket  lays the candidates out by bucket, best first;
+//   k_gftt_select  one workgroup per frame: windows of the best remaining
+//                  candidates are found from the bucket counts and, inside
+//                  the last bucket a window reaches, by radix selection on the
+//                  96-bit rank key (R bits, then the complemented raster
+//                  index); they are sorted in LDS and accepted 512 at a time
+//                  against the corners taken so far and the occupied points.
+//                  The acceptance within a chunk resolves the greedy rule
+//                  exactly (a candidate is taken iff no better candidate that
+//                  is taken lies too close).
 #include "lk_internal.h"
 
 namespace lkmi {
@@ -41,6 +44,27 @@ __device__ __forceinline__ int reflect101(int i, int n)
     return i;
 }
 
+// Correctly rounded square root of x, for x = 0 or x >= 1 (the discriminant
+// below is a sum of squares of integers): the hardware reciprocal square root
+// refined by Markstein's method (one Newton step on the pair (sqrt x,
+// 1/(2 sqrt x)), then two corrections by the exact residual x - s^2, each one
+// fused operation).  This is the compiler's own sequence for sqrt without its
+// rescaling of tiny and huge arguments, which never applies here, so the
+// results are its results, bit for bit.
+__device__ __forceinline__ double sqrt_ge1(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-h, s, 0.5);
+    s = __builtin_fma(s, r, s);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-s, s, x);
+    s = __builtin_fma(d, h, s);
+    d = __builtin_fma(-s, s, x);
+    s = __builtin_fma(d, h, s);
+    return x == 0.0 ? 0.0 : s;
+}
+
 // Smaller eigenvalue of [a b; b c] in binary64, one rounding per operation in
 // the order fixed by the definition (contraction into fused operations is
 // switched off for this function).
@@ -52,9 +76,50 @@ __device__ __forceinline__ double min_eig(int32_t a, int32_t b, int32_t c)
     const double d1 = t * t;
     const double d2 = (4.0 * u) * u;
     const double disc = d1 + d2;
-    const double s = __builtin_sqrt(disc);
+    const double s = sqrt_ge1(disc);
     const double tr = (double)(a + c);
     return (tr - s) * 0.5;
+}
+
+// The rank key of a candidate: 96 bits, R bits then the complemented raster
+// index (larger = earlier), so the order is total.  Digits are 8-bit fields
+// at any bit position p (0 = the most significant bit), read from the key
+// aligned to the top of 128 bits.
+struct Key {
+    unsigned long long hi;   // bits of R (R > 0, so the bits order like R)
+    uint32_t lo;             // complemented raster index
+};
+
+__device__ __forceinline__ bool key_less(Key a, Key b)
+{
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+__device__ __forceinline__ unsigned __int128 key_top(Key k)
+{
+    return ((unsigned __int128)k.hi << 64) | ((unsigned __int128)k.lo << 32);
+}
+
+// bits [p, p + 8) of the key, 0 <= p < 96 (bits past the key read as 0)
+__device__ __forceinline__ uint32_t key_digit(Key k, int p)
+{
+    return (uint32_t)((key_top(k) << p) >> 120);
+}
+
+// the leading p bits of k and q agree, 0 <= p <= 96
+__device__ __forceinline__ bool key_prefix_eq(Key k, Key q, int p)
+{
+    return p == 0 || ((key_top(k) ^ key_top(q)) >> (128 - p)) == 0;
+}
+
+// q's leading p bits, then digit v, then zeros: the least key whose digit at
+// p is v among those with q's leading p bits, 0 <= p < 96
+__device__ __forceinline__ Key key_with_digit(Key q, int p, uint32_t v)
+{
+    unsigned __int128 t = key_top(q);
+    t = p == 0 ? (unsigned __int128)0 : (t >> (128 - p)) << (128 - p);
+    t |= (unsigned __int128)(v & 0xFFu) << (120 - p);
+    return Key{(unsigned long long)(t >> 64), (uint32_t)(t >> 32)};
 }
 
 template <int R>
@@ -209,6 +274,288 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
     }
 }
 
+// ---- responses and peaks, block radius 0 and 1: one wavefront per strip ------
+//
+// A strip is 60 output columns x 64 output rows; lane i owns frame column
+// X = x0 - 2 + i and walks down the rows.  Per row it forms the Scharr
+// gradient of its column from the staged frame bytes (at the reflect-101
+// position, as the tiled kernel does), the three products, their horizontal
+// (2r+1)-sums over neighbouring lanes by wave-shift DPP, and their vertical
+// sums over the last 2r+1 rows in registers; the response follows from the
+// sums as in the tiled kernel.  Non-maximum suppression is separable: the
+// maximum over a 3x3 block is the maximum of three row maxima, each the
+// maximum of a lane and its two neighbours (again by wave shifts), and a
+// response is a local maximum iff it equals that maximum (no response is
+// NaN).  Lanes 0 and 63 hold no valid sums, lanes 1 and 62 no valid maxima:
+// lanes 2 .. 61 produce the strip's 60 columns.  Same integers, same binary64
+// operations, same comparisons as the tiled kernel: the same response map
+// and peaks, bit for bit.
+
+constexpr int kStripWaves = 1;                // strips per workgroup, one per wavefront
+
+template <int R>
+struct alignas(16) StripSmem {
+    static constexpr int IH = kGfttStripH + 2 * R + 4, IW = 80;   // frame rows y0-2-R.., columns sx0..
+    static constexpr int NBUF = 128;
+    uint8_t img[IH][IW];
+    GfttPeak buf[NBUF];                                           // peaks waiting for a global slot
+};
+
+// Lane i's value from lane i - 1 (wave_shr:1) and from lane i + 1
+// (wave_shl:1); the end lanes, which have no such neighbour, get 0.
+__device__ __forceinline__ int32_t from_left(int32_t v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int32_t from_right(int32_t v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }
+
+// a * b for |a|, |b| < 2^23 with a product that fits 32 bits (the gradients:
+// |g| <= 4080): the full-rate 24-bit multiply, which the compiler does not
+// pick by itself here
+__device__ __forceinline__ int32_t mul_i24(int32_t a, int32_t b)
+{
+    int32_t p;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(p) : "v"(a), "v"(b));
+    return p;
+}
+
+// a * b + c, same conditions
+__device__ __forceinline__ int32_t mad_i24(int32_t a, int32_t b, int32_t c)
+{
+    int32_t p;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(p) : "v"(a), "v"(b), "v"(c));
+    return p;
+}
+
+// max of two responses.  No response is NaN, so the quieting fmax asks of
+// its operands is not needed: the plain instruction.
+__device__ __forceinline__ double max_r(double a, double b)
+{
+    double m;
+    asm("v_max_f64 %0, %1, %2" : "=v"(m) : "v"(a), "v"(b));
+    return m;
+}
+
+// max of a lane's response and those of its two neighbours (0 at the end
+// lanes, whose maxima are not used)
+__device__ __forceinline__ double max3_lanes(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int32_t lo = (int32_t)(uint32_t)u, hi = (int32_t)(uint32_t)(u >> 32);
+    const double l = __longlong_as_double((long long)(((unsigned long long)(uint32_t)from_left(hi) << 32) |
+                                                       (uint32_t)from_left(lo)));
+    const double r = __longlong_as_double((long long)(((unsigned long long)(uint32_t)from_right(hi) << 32) |
+                                                       (uint32_t)from_right(lo)));
+    return max_r(v, max_r(l, r));
+}
+
+template <int R>
+__global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const GfttJob *__restrict__ jobs,
+                                                                      const int32_t *__restrict__ tile_job,
+                                                                      int n_tiles, int border)
+{
+    static_assert(R == 0 || R == 1, "block radius 0 or 1");
+    using S = StripSmem<R>;
+    __shared__ S sms[kStripWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    S &sm = sms[wv];
+    // strips of one workgroup are consecutive; a wavefront past the last one
+    // stages the last one again and leaves after the barrier
+    const int tile_w = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStripWaves + wv);
+    const bool has = tile_w < n_tiles;
+    const int tile = has ? tile_w : n_tiles - 1;
+    const GfttJob J = jobs[__builtin_amdgcn_readfirstlane(tile_job[tile])];
+    const int t = tile - J.tile_begin;
+    const int W = J.w, H = J.h;
+    const int x0 = (t % J.tiles_x) * kGfttStripW, y0 = (t / J.tiles_x) * kGfttStripH;
+    const int sx0 = (x0 - 3) & ~7, sy0 = y0 - 2 - R;
+    // 1. frame rows [sy0, sy0 + IH) x columns [sx0, sx0 + 80) as bytes (the
+    //    walk reads columns x0 - 3 .. x0 + 62), 8-byte loads; a sample
+    //    outside the frame holds its reflect-101 sample (only those at
+    //    distance 1 are ever read)
+    {
+        const bool vec_ok = (J.pitch & 7) == 0 && (reinterpret_cast<uintptr_t>(J.img) & 7) == 0;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(J.img), (short)0, J.pitch * H, 0x00020000);
+        for (int e = lane; e < S::IH * (S::IW / 8); e += 64) {
+            const int j = e / (S::IW / 8), c = e - j * (S::IW / 8);
+            const int Y = reflect1(min(max(sy0 + j, -2), H + 1), H);
+            const int X0 = sx0 + 8 * c;
+            if (vec_ok && X0 >= 0 && X0 + 8 <= W) {
+                *reinterpret_cast<uint2 *>(&sm.img[j][8 * c]) =
+                    __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, Y * J.pitch + X0, 0, 0));
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int X = reflect1(min(max(X0 + k, -2), W + 1), W);
+                    sm.img[j][8 * c + k] = J.img[(size_t)Y * J.pitch + X];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!has) return;
+    // 2. the walk.  Column X of this lane; its gradient slot is formed when
+    //    the sums can reach it (X in [-1-R, W+R)), at the reflect-101 column.
+    const int X = x0 - 2 + lane;
+    const bool xslot = X >= -1 - R && X < W + R;
+    const int xc = (xslot ? reflect101(X, W) : 0) - sx0;       // staged column of the gradient's centre
+    const bool xout = lane >= 2 && lane < 62 && X < W;          // an output column of the strip
+    const bool xin = X >= 0 && X < W;
+    const int ye = min(y0 + kGfttStripH, H);                    // output rows y0 .. ye-1
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    double vmax = 0.0;
+    uint32_t nbuf = 0;                                          // peaks in sm.buf (wave-uniform)
+    auto flush = [&]() {
+        uint32_t base = 0;
+        if (lane == 0) base = (uint32_t)atomicAdd(J.n_peaks, (int)nbuf);
+        base = __shfl(base, 0, 64);
+        __builtin_amdgcn_wave_barrier();                        // entries of the other lanes
+        for (uint32_t k = lane; k < nbuf; k += 64) J.peaks[base + k] = sm.buf[k];
+        __builtin_amdgcn_wave_barrier();
+        nbuf = 0;
+    };
+    // The walk, in two forms.  Where every gradient row of the strip lies in
+    // [0, H) (strips away from the top and bottom edges) the staged rows of
+    // consecutive gradient rows are consecutive, and the separable form of the
+    // Scharr gradient rolls: with d(j) = I(j, x+1) - I(j, x-1) and
+    // s(j) = 3 I(j, x-1) + 10 I(j, x) + 3 I(j, x+1) on staged row j,
+    // gx = 3 d(j-1) + 10 d(j) + 3 d(j+1) and gy = s(j+1) - s(j-1), and each
+    // gradient row reads one new staged row.  Elsewhere each gradient row
+    // reads its 3x3 taps at the reflect-101 row.
+    auto walk = [&](auto roll_tag) {
+        constexpr bool ROLL = decltype(roll_tag)::value;
+        int32_t hxx[3] = {0, 0, 0}, hxy[3] = {0, 0, 0}, hyy[3] = {0, 0, 0};   // products of gradient rows
+        int32_t hd[3] = {0, 0, 0}, hs[3] = {0, 0, 0};          // d and s of three staged rows (ROLL)
+        auto row_taps = [&](int j, int32_t &d, int32_t &sj) {
+            const int l = sm.img[j][xc - 1], c = sm.img[j][xc], r = sm.img[j][xc + 1];
+            d = r - l;
+            sj = 3 * (l + r) + 10 * c;
+        };
+        // Gradient row Yg into product slot (O + 2) % 3 (slot 0 for R = 0).
+        // Ring roles (ROLL): staged rows yc - 1, yc, yc + 1 in slots O, O + 1,
+        // O + 2 (mod 3); calls with O = 0, 1, 2, 0, ... on consecutive rows.
+        auto grad_row = [&](auto o_slot, int Yg) {
+            constexpr int O = decltype(o_slot)::value, M = (O + 1) % 3, N = (O + 2) % 3;
+            constexpr int P = R == 1 ? N : 0;
+            int32_t pxx = 0, pxy = 0, pyy = 0;
+            if constexpr (ROLL) {
+                if (xslot) {
+                    row_taps(Yg - sy0 + 1, hd[N], hs[N]);
+                    const int gx = mad_i24(3, hd[O] + hd[N], mul_i24(10, hd[M]));
+                    const int gy = hs[N] - hs[O];
+                    pxx = mul_i24(gx, gx);
+                    pxy = mul_i24(gx, gy);
+                    pyy = mul_i24(gy, gy);
+                }
+            } else {
+                if (xslot && Yg >= -1 - R && Yg < H + R) {
+                    const int yc = reflect101(Yg, H) - sy0;
+                    const int a00 = sm.img[yc - 1][xc - 1], a01 = sm.img[yc - 1][xc], a02 = sm.img[yc - 1][xc + 1];
+                    const int a10 = sm.img[yc][xc - 1], a12 = sm.img[yc][xc + 1];
+                    const int a20 = sm.img[yc + 1][xc - 1], a21 = sm.img[yc + 1][xc], a22 = sm.img[yc + 1][xc + 1];
+                    const int gx = 3 * (a02 - a00) + 10 * (a12 - a10) + 3 * (a22 - a20);
+                    const int gy = 3 * (a20 - a00) + 10 * (a21 - a01) + 3 * (a22 - a02);
+                    pxx = mul_i24(gx, gx);
+                    pxy = mul_i24(gx, gy);
+                    pyy = mul_i24(gy, gy);
+                }
+            }
+            if constexpr (R == 1) {
+                pxx += from_left(pxx) + from_right(pxx);
+                pxy += from_left(pxy) + from_right(pxy);
+                pyy += from_left(pyy) + from_right(pyy);
+            }
+            hxx[P] = pxx;
+            hxy[P] = pxy;
+            hyy[P] = pyy;
+        };
+        // Rows are walked three at a time with every ring slot a fixed
+        // register: step k (response row Yr = y0 - 1 + k) puts the horizontal
+        // sums of gradient row Yr + R in slot (k + 2) % 3 (R = 1: slots 0 and 1
+        // start with rows y0 - 2 and y0 - 1; R = 0 uses slot 0 alone), its
+        // response and row maximum in slot k % 3, and reads the previous row's
+        // response from slot (k + 2) % 3.  The block sum and the 3x3 maximum
+        // are symmetric in the slots, so no register moves between rows.
+        if constexpr (ROLL) {
+            // the first gradient row (y0 - 1 - R, staged row 1) has ring slot
+            // O = 1 (R = 1) or 0 (R = 0): its staged rows 0 and 1 first
+            constexpr int O0 = R == 1 ? 1 : 0;
+            if (xslot) {
+                row_taps(0, hd[O0], hs[O0]);
+                row_taps(1, hd[(O0 + 1) % 3], hs[(O0 + 1) % 3]);
+            }
+        }
+        if constexpr (R == 1) {
+            grad_row(S1{}, y0 - 2);                             // into product slot 0
+            grad_row(S2{}, y0 - 1);                             // slot 1
+        }
+        double rr[3] = {0.0, 0.0, 0.0}, mm[3] = {0.0, 0.0, 0.0};
+        auto step = [&](auto w_slot, auto p_slot, int Yr, bool out) {
+            constexpr int Ws = decltype(w_slot)::value, Ps = decltype(p_slot)::value;
+            grad_row(w_slot, Yr + R);                           // product slot Ps (R = 1)
+            double v = -__builtin_inf();
+            if (xin && Yr >= 0 && Yr < H) {
+                const int32_t a = R == 1 ? hxx[0] + hxx[1] + hxx[2] : hxx[0];
+                const int32_t b = R == 1 ? hxy[0] + hxy[1] + hxy[2] : hxy[0];
+                const int32_t c = R == 1 ? hyy[0] + hyy[1] + hyy[2] : hyy[0];
+                v = min_eig(a, b, c);
+            }
+            mm[Ws] = max3_lanes(v);
+            if (out) {
+                // output row Yr - 1: the response of row Yr - 1 against the 3x3 maximum
+                const int Yo = Yr - 1;
+                const double r = rr[Ps];
+                bool peak = false;
+                if (xout) {
+                    if (J.response) J.response[(size_t)Yo * W + X] = r;
+                    if (r > vmax) vmax = r;
+                    const double mx = max_r(mm[0], max_r(mm[1], mm[2]));
+                    peak = r > 0.0 && r == mx && X >= border && Yo >= border && X < W - border && Yo < H - border;
+                }
+                const unsigned long long bal = __ballot(peak);
+                if (bal) {
+                    if (peak) {
+                        GfttPeak pk;
+                        pk.rbits = (unsigned long long)__double_as_longlong(r);
+                        pk.idx = (uint32_t)(Yo * W + X);
+                        pk.pad = 0;
+                        sm.buf[nbuf + (uint32_t)__popcll(bal & ((1ull << lane) - 1))] = pk;
+                    }
+                    nbuf += (uint32_t)__popcll(bal);
+                    if (nbuf > S::NBUF - 64) flush();           // a full row must still fit
+                }
+            }
+            rr[Ws] = v;
+        };
+        step(S0{}, S2{}, y0 - 1, false);                        // rows y0 - 1 and y0: no output yet
+        step(S1{}, S0{}, y0, false);
+        for (int Yr = y0 + 1;; Yr += 3) {                       // ye >= y0 + 1
+            step(S2{}, S1{}, Yr, true);
+            if (Yr + 1 > ye) break;
+            step(S0{}, S2{}, Yr + 1, true);
+            if (Yr + 2 > ye) break;
+            step(S1{}, S0{}, Yr + 2, true);
+            if (Yr + 3 > ye) break;
+        }
+    };
+    // gradient rows y0 - 1 - R .. ye + R
+    if (y0 - 1 - R >= 0 && ye + R <= H - 1)
+        walk(std::true_type{});
+    else
+        walk(std::false_type{});
+    // the rest of the peaks, and the strip's maximum (one atomic each)
+    {
+        if (nbuf) flush();
+        unsigned long long mb = (unsigned long long)__double_as_longlong(vmax);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const unsigned long long other = __shfl_xor(mb, o, 64);
+            mb = other > mb ? other : mb;
+        }
+        if (lane == 0 && mb) atomicMax(J.max_bits, mb);
+    }
+}
+
 // ---- threshold --------------------------------------------------------------
 //
 // The threshold needs the frame maximum, known only once every tile is done:
@@ -355,52 +702,35 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
     const double thr = quality * __longlong_as_double((long long)max_bits);
     const unsigned long long thr_bits = (unsigned long long)__double_as_longlong(thr);
     // the candidates' R bits lie in (thr_bits, max_bits]: they share the
-    // leading d0 bytes of those two, and byte d0 is histogrammed for the
-    // selection's first radix pass
+    // leading lz bits of those two (none exist when the two are equal), and
+    // the 8 key bits after those, their bucket, are histogrammed
     const unsigned long long diff = max_bits ^ thr_bits;
-    const int d0 = diff ? (__clzll((long long)diff) >> 3) : 8;
-    const int hshift = d0 < 8 ? 56 - 8 * d0 : 0;
+    const int lz = diff ? __clzll((long long)diff) : 64;
     __syncthreads();                           // s_hist is cleared (when no grid was built)
-    // this workgroup's slice of the frame's peaks, in steps of BLOCK
+    // this workgroup's slice of the frame's peaks, read once, CB per thread
+    // at a time; each batch's kept peaks get one range of the candidate list
+    // (one global atomic), wavefronts in turn, lanes by their ballot prefix
+    // (the order does not matter: the selection ranks by the total key)
     const int per = (np + gridDim.x - 1) / gridDim.x;
     const int k_lo = min(np, (int)blockIdx.x * per), k_hi = min(np, k_lo + per);
-    uint32_t mine = 0;
-    for (int k0 = k_lo; k0 < k_hi; k0 += BLOCK) {
-        const int k = k0 + threadIdx.x;
-        if (k < k_hi) {
-            const GfttPeak p = J.peaks[k];
-            if (p.rbits > thr_bits && kept(p)) {
-                mine += 1u;
-                if (d0 < 8) atomicAdd(&s_hist[(uint32_t)(p.rbits >> hshift) & 0xFFu], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    if (d0 < 8 && s_hist[threadIdx.x]) atomicAdd(&J.hist[threadIdx.x], s_hist[threadIdx.x]);
-    // wavefront and workgroup totals, one global atomic
-    uint32_t wsum = mine;
+    constexpr int CB = 8;
+    for (int k0 = k_lo; k0 < k_hi; k0 += CB * BLOCK) {
+        GfttPeak p[CB];
+        unsigned long long m[CB];
+        uint32_t wc = 0;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) wsum += __shfl_xor(wsum, o, 64);
-    if (lane == 0) s_cnt[wv] = wsum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < BLOCK / 64; ++w) tot += s_cnt[w];
-        s_base = tot ? (uint32_t)atomicAdd(J.n_cand, (int)tot) : 0u;
-    }
-    __syncthreads();
-    // write in the same order: wavefronts in turn, lanes by their prefix
-    uint32_t base = s_base;
-    for (int k0 = k_lo; k0 < k_hi; k0 += BLOCK) {
-        const int k = k0 + threadIdx.x;
-        GfttPeak p{};
-        bool keep = false;
-        if (k < k_hi) {
-            p = J.peaks[k];
-            keep = p.rbits > thr_bits && kept(p);
+        for (int i = 0; i < CB; ++i) {
+            const int k = k0 + i * BLOCK + (int)threadIdx.x;
+            p[i] = k < k_hi ? J.peaks[k] : GfttPeak{};
         }
-        const unsigned long long m = __ballot(keep);
-        uint32_t wc = (uint32_t)__popcll(m);
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int k = k0 + i * BLOCK + (int)threadIdx.x;
+            const bool keep = k < k_hi && p[i].rbits > thr_bits && kept(p[i]);
+            if (keep && lz < 64) atomicAdd(&s_hist[key_digit(Key{p[i].rbits, ~p[i].idx}, lz)], 1u);
+            m[i] = __ballot(keep);
+            wc += (uint32_t)__popcll(m[i]);
+        }
         if (lane == 0) s_cnt[wv] = wc;
         __syncthreads();
         uint32_t before = 0, all = 0;
@@ -410,8 +740,90 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
             before += w < wv ? c : 0u;
             all += c;
         }
-        if (keep) J.cand[base + before + (uint32_t)__popcll(m & ((1ull << lane) - 1))] = p;
-        base += all;
+        if (threadIdx.x == 0) s_base = all ? (uint32_t)atomicAdd(J.n_cand, (int)all) : 0u;
+        __syncthreads();
+        uint32_t at = s_base + before;
+        const unsigned long long lt = (1ull << lane) - 1;
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            if ((m[i] >> lane) & 1ull) J.cand[at + (uint32_t)__popcll(m[i] & lt)] = p[i];
+            at += (uint32_t)__popcll(m[i]);
+        }
+        __syncthreads();                       // s_cnt and s_base are reused
+    }
+    if (lz < 64 && s_hist[threadIdx.x]) atomicAdd(&J.hist[threadIdx.x], s_hist[threadIdx.x]);
+}
+
+// ---- candidates by bucket -----------------------------------------------------
+//
+// A candidate's bucket is the byte of its R bits that the compaction
+// histogrammed.  This grid (gridDim.x workgroups per frame) lays the frame's
+// candidates out in the peak list by bucket, larger buckets first (in any
+// order within a bucket): every bucket, and every run of buckets, is then one
+// contiguous range, and the selection reads only the buckets a window can
+// reach instead of every candidate.
+__global__ __launch_bounds__(BLOCK) void k_gftt_bucket(const GfttJob *__restrict__ jobs, double quality)
+{
+    __shared__ uint32_t s_pos[256], s_cnt[256], s_wsum[BLOCK / 64];
+    const GfttJob &J = jobs[blockIdx.y];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nc = *J.n_cand;
+    if (nc == 0) return;                       // (then the bucket byte may not exist)
+    const unsigned long long max_bits = *J.max_bits;
+    const unsigned long long thr_bits =
+        (unsigned long long)__double_as_longlong(quality * __longlong_as_double((long long)max_bits));
+    // candidates exist, so thr_bits < max_bits
+    const int lz = __clzll((long long)(max_bits ^ thr_bits));
+    // start of bucket b = the candidates in buckets above b: thread t scans
+    // bucket 255 - t
+    const uint32_t h = J.hist[255 - tid];
+    uint32_t incl = h;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_wsum[wv] = incl;
+    s_cnt[tid] = 0u;
+    __syncthreads();
+    uint32_t start = incl - h;
+    for (int w = 0; w < wv; ++w) start += s_wsum[w];
+    // this workgroup's slice, read once, CB per thread at a time: counted by
+    // bucket, a range of each bucket reserved (one global atomic per bucket
+    // the batch holds), then written
+    const int per = (nc + gridDim.x - 1) / gridDim.x;
+    const int k_lo = min(nc, (int)blockIdx.x * per), k_hi = min(nc, k_lo + per);
+    constexpr int CB = 8;
+    for (int k0 = k_lo; k0 < k_hi; k0 += CB * BLOCK) {
+        GfttPeak p[CB];
+        uint32_t d[CB];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int k = k0 + i * BLOCK + tid;
+            p[i] = k < k_hi ? J.cand[k] : GfttPeak{};
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int k = k0 + i * BLOCK + tid;
+            d[i] = key_digit(Key{p[i].rbits, ~p[i].idx}, lz);
+            if (k < k_hi) atomicAdd(&s_cnt[d[i]], 1u);
+        }
+        __syncthreads();
+        {
+            const int b = 255 - tid;
+            const uint32_t c = s_cnt[b];
+            s_pos[b] = c ? start + (uint32_t)atomicAdd(&J.cursor[b], c) : 0u;
+        }
+        __syncthreads();
+        s_cnt[tid] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int k = k0 + i * BLOCK + tid;
+            if (k < k_hi) J.peaks[s_pos[d[i]] + atomicAdd(&s_cnt[d[i]], 1u)] = p[i];
+        }
+        __syncthreads();
+        s_cnt[tid] = 0u;                       // (read by no thread before the next barrier)
         __syncthreads();
     }
 }
@@ -422,45 +834,6 @@ constexpr int CAPW = kGfttWindow;             // window of peaks sorted in LDS
 constexpr int TG_CELLS = 2048;                // cells of the taken-corner grid, at most
 constexpr int SBLOCK = 512;                   // threads of the selection workgroup
 constexpr int CHUNK = SBLOCK;                 // candidates decided together
-struct Key {
-    unsigned long long hi;   // bits of R (R > 0, so the bits order like R)
-    uint32_t lo;             // complemented raster index: larger = earlier
-};
-
-__device__ __forceinline__ bool key_less(Key a, Key b)
-{
-    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
-}
-
-__device__ __forceinline__ uint32_t key_byte(Key k, int d)
-{
-    return d < 8 ? (uint32_t)(k.hi >> (56 - 8 * d)) & 0xFFu : (k.lo >> (24 - 8 * (d - 8))) & 0xFFu;
-}
-
-// Keys whose leading d bytes equal those of p.
-__device__ __forceinline__ bool key_prefix_eq(Key k, Key p, int d)
-{
-    if (d == 0) return true;
-    if (d <= 8) {
-        const unsigned long long m = d == 8 ? ~0ull : ~((1ull << (64 - 8 * d)) - 1);
-        return (k.hi & m) == (p.hi & m);
-    }
-    const uint32_t m = d == 12 ? ~0u : ~((1u << (32 - 8 * (d - 8))) - 1);
-    return k.hi == p.hi && (k.lo & m) == (p.lo & m);
-}
-
-__device__ __forceinline__ Key key_set_byte(Key k, int d, uint32_t v)
-{
-    if (d < 8) {
-        const int s = 56 - 8 * d;
-        k.hi = (k.hi & ~(0xFFull << s)) | ((unsigned long long)v << s);
-    } else {
-        const int s = 24 - 8 * (d - 8);
-        k.lo = (k.lo & ~(0xFFu << s)) | (v << s);
-    }
-    return k;
-}
-
 struct alignas(16) SelSmem {
     unsigned long long whi[CAPW];
     uint32_t wlo[CAPW];
@@ -472,6 +845,9 @@ struct alignas(16) SelSmem {
     uint32_t hist[SBLOCK / 64][256];           // one histogram per wavefront
     unsigned long long cmask[CHUNK][CHUNK / 64];   // conflicts with better candidates of the chunk
     unsigned long long sel[CHUNK / 64], und[CHUNK / 64];
+    uint32_t bstart[256], bcnt[256];           // the list range of each bucket
+    uint32_t bwsum[4];
+    int32_t bb, be;
     uint32_t wcount, bcount;
     Key bound;
     int32_t done_flag;
@@ -546,13 +922,40 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     const int md2 = min_dist * min_dist;
     const double md2d = (double)md2;
     const bool spaced = min_dist >= 2;         // distinct pixels are always >= 1 apart
-    const GfttPeak *cand = J.cand;
+    const GfttPeak *list = J.peaks;           // the candidates by bucket
     const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
     // every candidate's R bits lie in (thr_bits, max_bits] (the threshold is
     // formed as the compaction forms it)
     const unsigned long long max_bits = *J.max_bits;
     const unsigned long long thr_bits =
         (unsigned long long)__double_as_longlong(quality * __longlong_as_double((long long)max_bits));
+    // they share the leading lz bits of those two (when the two are equal
+    // there are none); the 8 key bits after those are their bucket, and
+    // bucket b holds list positions [bstart[b], bstart[b] + bcnt[b]), larger
+    // buckets first
+    const unsigned long long diff0 = max_bits ^ thr_bits;
+    const int lz = diff0 ? __clzll((long long)diff0) : 63;
+    const Key shared{max_bits, 0};              // (its leading lz bits)
+    {
+        uint32_t h = 0, incl = 0;              // thread t < 256 scans bucket 255 - t
+        if (tid < 256) {
+            h = J.hist[255 - tid];
+            incl = h;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            if (lane == 63) sm.bwsum[wv] = incl;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t start = incl - h;
+            for (int w = 0; w < wv; ++w) start += sm.bwsum[w];
+            sm.bstart[255 - tid] = start;
+            sm.bcnt[255 - tid] = h;
+        }
+    }
 
     const TakenGrid T = taken_grid(W, J.h, min_dist);
     for (int c = tid; c < TG_CELLS; c += SBLOCK) sm.tg_head[c] = -1;
@@ -564,43 +967,45 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     __syncthreads();
 
     while (nt < max_corners && remaining > 0) {
-        // ---- the next window: the best min(CAPW, remaining) candidates
+        // ---- the next window: the best min(CAPW, remaining) candidates,
+        // ranks [consumed, consumed + wn) of the descending order
+        const int consumed = np - remaining;
         const int wn = remaining < CAPW ? remaining : CAPW;
-        Key low{0, 0};                          // window = eligible keys >= low
-        // the list the passes read: the candidates, or, once few keys are at
-        // or above the boundary bucket, a copy of just those keys (in the
-        // frame's peak list, no longer needed after the compaction)
-        const GfttPeak *src = cand;
-        int nsrc = np;
-        bool filtered = false;
-        if (wn < remaining) {
-            uint32_t need = (uint32_t)wn;
-            // the eligible keys' R bits lie in (thr_bits, top]: their leading
-            // bytes are those thr_bits and top share, so the passes start
-            // after them
-            const unsigned long long top = bounded ? bound.hi : max_bits;
-            const unsigned long long diff = top ^ thr_bits;
-            const int d0 = diff ? (__clzll((long long)diff) >> 3) : 8;
-            Key prefix{d0 >= 8 ? top : (d0 == 0 ? 0ull : top & ~((1ull << (64 - 8 * d0)) - 1)), 0};
-            for (int d = d0; d < 12; ++d) {
+        if (tid < 256) {
+            const int b0 = (int)sm.bstart[tid], b1 = b0 + (int)sm.bcnt[tid];
+            if (b0 <= consumed && consumed < b1) sm.bb = tid;
+            if (b0 <= consumed + wn - 1 && consumed + wn - 1 < b1) sm.be = tid;
+        }
+        __syncthreads();
+        const int bb = sm.bb & 255, be = sm.be & 255;   // buckets of the first and the last rank, bb >= be
+        // the window's keys: every eligible key of buckets bb .. be + 1 (list
+        // range A) and those of bucket be (range B) that are >= low
+        const int a_lo = (int)sm.bstart[bb], a_hi = (int)sm.bstart[be];
+        const GfttPeak *srcB = list + sm.bstart[be];
+        int nB = (int)sm.bcnt[be];
+        const Key bucket_low = key_with_digit(shared, lz, (uint32_t)be);
+        Key low = wn < remaining ? bucket_low : Key{0, 0};
+        if (wn < remaining && consumed + wn < (int)(sm.bstart[be] + sm.bcnt[be])) {
+            // the window ends inside bucket be: radix selection of its best
+            // `need` eligible keys, by the digits after the bucket's
+            const uint32_t need_be = (uint32_t)(consumed + wn - max(consumed, (int)sm.bstart[be]));
+            uint32_t need = need_be;
+            Key prefix = bucket_low;
+            bool filtered = false;
+            for (int d = lz + 8; d < 96; d += 8) {
                 for (int k = tid; k < (SBLOCK / 64) * 256; k += SBLOCK) (&sm.hist[0][0])[k] = 0;
                 __syncthreads();
-                // the first window's first digit: every candidate is eligible
-                // and carries the prefix, so the compaction's histogram is
-                // this pass's count
-                const bool counted = d == d0 && !bounded && d0 < 8;
-                if (counted && tid < 256) sm.hist[0][tid] = J.hist[tid];
-                for (int k0 = 0; k0 < (counted ? 0 : nsrc); k0 += 8 * SBLOCK) {
+                for (int k0 = 0; k0 < nB; k0 += 8 * SBLOCK) {
                     Key key[8];
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int k = k0 + i * SBLOCK + tid;
-                        key[i] = k < nsrc ? Key{src[k].rbits, ~src[k].idx} : Key{0, 0};
+                        key[i] = k < nB ? Key{srcB[k].rbits, ~srcB[k].idx} : Key{0, 0};
                     }
 #pragma unroll
                     for (int i = 0; i < 8; ++i)
                         if (key[i].hi != 0 && eligible(key[i], bounded, bound) && key_prefix_eq(key[i], prefix, d))
-                            atomicAdd(&sm.hist[wv][key_byte(key[i], d)], 1u);
+                            atomicAdd(&sm.hist[wv][key_digit(key[i], d)], 1u);
                 }
                 __syncthreads();
                 if (wv == 0) {
@@ -613,21 +1018,19 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                         for (int w = 0; w < SBLOCK / 64; ++w) t[i] += sm.hist[w][4 * lane + i];
                         ls += t[i];
                     }
-                    uint32_t above = 0;              // sum over lanes > lane
                     uint32_t run = ls;
 #pragma unroll
                     for (int o = 1; o < 64; o <<= 1) {
                         const uint32_t v = __shfl_down(run, o, 64);
                         if (lane + o < 64) run += v;
                     }
-                    above = run - ls;
-                    uint32_t cum = above;
+                    uint32_t cum = run - ls;             // sum over lanes > lane
 #pragma unroll
                     for (int i = 3; i >= 0; --i) {
                         if (cum < need && need <= cum + t[i]) {
                             sm.need = need - cum;
                             sm.done_flag = t[i] == need - cum ? 1 : 0;
-                            sm.bound = key_set_byte(prefix, d, (uint32_t)(4 * lane + i));
+                            sm.bound = key_with_digit(prefix, d, (uint32_t)(4 * lane + i));
                             sm.bcount = t[i];
                         }
                         cum += t[i];
@@ -637,34 +1040,33 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 need = sm.need;
                 prefix = sm.bound;
                 const bool whole = sm.done_flag != 0;
-                const int kept = (int)((uint32_t)wn - need + sm.bcount);   // keys >= the bucket's lower bound
+                const int kept = (int)(need_be - need + sm.bcount);   // bucket keys >= the new prefix
                 __syncthreads();
                 if (whole) break;
-                if (!filtered && 4 * kept <= nsrc) {
-                    // copy the eligible keys >= prefix (its lower bytes are 0):
-                    // the keys above the bucket and the bucket itself
+                if (!filtered && 4 * kept <= nB) {
+                    // copy bucket be's eligible keys >= prefix (its lower bytes
+                    // are 0) to the scratch list, 8 keys per thread in flight
                     if (tid == 0) sm.wcount = 0;
                     __syncthreads();
-                    // (8 keys per thread in flight, as in the counting passes)
-                    for (int k0 = 0; k0 < nsrc; k0 += 8 * SBLOCK) {
-                        GfttPeak p[8];
+                    for (int k0 = 0; k0 < nB; k0 += 8 * SBLOCK) {
+                        GfttPeak pk[8];
 #pragma unroll
                         for (int i = 0; i < 8; ++i) {
                             const int k = k0 + i * SBLOCK + tid;
-                            p[i] = k < nsrc ? src[k] : GfttPeak{};
+                            pk[i] = k < nB ? srcB[k] : GfttPeak{};
                         }
 #pragma unroll
                         for (int i = 0; i < 8; ++i) {
                             const int k = k0 + i * SBLOCK + tid;
-                            const Key key{p[i].rbits, ~p[i].idx};
-                            const bool take = k < nsrc && eligible(key, bounded, bound) && !key_less(key, prefix);
+                            const Key key{pk[i].rbits, ~pk[i].idx};
+                            const bool take = k < nB && eligible(key, bounded, bound) && !key_less(key, prefix);
                             const uint32_t at = wave_append(take, &sm.wcount);
-                            if (take) J.peaks[at] = p[i];
+                            if (take) J.cand[at] = pk[i];
                         }
                     }
                     __syncthreads();             // the copy is visible to the whole workgroup
-                    src = J.peaks;
-                    nsrc = (int)sm.wcount;
+                    srcB = J.cand;
+                    nB = (int)sm.wcount;
                     filtered = true;
                     __syncthreads();
                 }
@@ -676,12 +1078,14 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
         if (tid == 0) sm.wcount = 0;
         __syncthreads();
         const bool screen = spaced && nt > 0;
-        for (int k0 = 0; k0 < nsrc; k0 += 8 * SBLOCK) {
+        const int nA = a_hi - a_lo, ngat = nA + nB;
+        for (int k0 = 0; k0 < ngat; k0 += 8 * SBLOCK) {
             Key key[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int k = k0 + i * SBLOCK + tid;
-                key[i] = k < nsrc ? Key{src[k].rbits, ~src[k].idx} : Key{0, 0};
+                const GfttPeak *q = k < nA ? list + a_lo + k : srcB + (k - nA);
+                key[i] = k < ngat ? Key{q->rbits, ~q->idx} : Key{0, 0};
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -881,6 +1285,7 @@ __global__ void k_gftt_reset(const GfttJob *__restrict__ jobs)
 {
     const GfttJob &J = jobs[blockIdx.x];
     J.hist[threadIdx.x] = 0u;
+    J.cursor[threadIdx.x] = 0u;
     if (threadIdx.x == 0) {
         *J.n_peaks = 0;
         *J.n_cand = 0;
@@ -895,13 +1300,21 @@ hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njo
 {
     if (njobs <= 0) return hipSuccess;
     k_gftt_reset<<<njobs, 256, 0, s>>>(d_jobs);
+    // the tile shape of each radius is the host's (gftt_tile_shape)
     switch (radius) {
-    case 0: k_gftt_peaks<0><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
-    case 1: k_gftt_peaks<1><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
+    case 0:
+        k_gftt_peaks_strip<0><<<(total_tiles + kStripWaves - 1) / kStripWaves, 64 * kStripWaves, 0, s>>>(
+            d_jobs, d_tile_job, total_tiles, border);
+        break;
+    case 1:
+        k_gftt_peaks_strip<1><<<(total_tiles + kStripWaves - 1) / kStripWaves, 64 * kStripWaves, 0, s>>>(
+            d_jobs, d_tile_job, total_tiles, border);
+        break;
     case 2: k_gftt_peaks<2><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     default: k_gftt_peaks<3><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     }
     k_gftt_compact<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality, min_dist);
+    k_gftt_bucket<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality);
     k_gftt_select<<<njobs, SBLOCK, 0, s>>>(d_jobs, quality, min_dist, max_corners);
     return hipGetLastError();
 }

@@ -107,13 +107,14 @@ struct GfttJob {
     int32_t n_occupied;
     const float *occupied;
     const int32_t *n_occupied_dev;   // nullable: the number of occupied points, read on the device
-    GfttPeak *peaks;                 // local maxima with R > 0, capacity w * h
+    GfttPeak *peaks;                 // local maxima with R > 0, then the candidates by bucket; capacity w * h
     int32_t *n_peaks;
-    GfttPeak *cand;                  // those above the quality threshold, capacity w * h
-    int32_t *n_cand;
+    GfttPeak *cand;                  // those above the quality threshold, then the selection's scratch;
+    int32_t *n_cand;                 // capacity w * h
     unsigned long long *max_bits;    // bits of max(0, max R)
     uint32_t *hist;                  // 256 bins: the candidates by the first byte of their R bits that the
-                                     // threshold and the maximum leave open (filled by the compaction)
+                                     // threshold and the maximum leave open (their bucket; the compaction's)
+    uint32_t *cursor;                // 256 fill counters of the buckets (the bucket layout's)
     float *out_xy;
     int32_t *count;
     double *response;                // nullable
@@ -157,7 +158,14 @@ struct EpiJob {
     int32_t wg_begin, pad;
 };
 
-constexpr int kGfttTileW = 64, kGfttTileH = 16;
+constexpr int kGfttTileW = 64, kGfttTileH = 16;      // response tiles, block radius 2 and 3
+constexpr int kGfttStripW = 60, kGfttStripH = 64;    // response strips of one wavefront, radius 0 and 1
+// Response tile (or strip) of a detection with block radius r.
+inline void gftt_tile_shape(int r, int *tw, int *th)
+{
+    *tw = r <= 1 ? kGfttStripW : kGfttTileW;
+    *th = r <= 1 ? kGfttStripH : kGfttTileH;
+}
 constexpr int kGfttWindow = 2048;             // peaks sorted per selection window
 constexpr int kGfttMaxCorners = LK_GFTT_MAX_CORNERS;
 
@@ -212,7 +220,8 @@ constexpr int kCounterBytes = 8 * kCounterStride * 4;
 hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int total_points, const TrackArgs &a,
                                    int storage, int *d_counters, int blocks_per_cu, int num_cus, int chunk,
                                    hipStream_t stream);
-// Detection of every frame in d_jobs (reset, peaks, selection: three launches).
+// Detection of every frame in d_jobs (reset, peaks, compaction, bucket layout,
+// selection: five launches).
 hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int radius,
                        int border, double quality, int min_dist, int max_corners, hipStream_t stream);
 // Track-pool lifecycle kernels (lk_pool_kernels.hip), one workgroup per stream.
