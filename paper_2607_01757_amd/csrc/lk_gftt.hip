@@ -834,12 +834,14 @@ constexpr int CAPW = kGfttWindow;             // window of peaks sorted in LDS
 constexpr int TG_CELLS = 2048;                // cells of the taken-corner grid, at most
 constexpr int SBLOCK = 512;                   // threads of the selection workgroup
 constexpr int CHUNK = SBLOCK;                 // candidates decided together
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
 struct alignas(16) SelSmem {
     unsigned long long whi[CAPW];
     uint32_t wlo[CAPW];
     uint32_t taken[kGfttMaxCorners + 16];     // x | y << 16
     OccGridSmem grid;                          // the cached occupied points
-    int32_t cx[CHUNK], cy[CHUNK];
+    uint32_t cxy[CHUNK];                       // packed candidates: x | y << 16
     int32_t tg_head[TG_CELLS];                 // taken corners by grid cell: first index, -1 for none
     int32_t tg_next[kGfttMaxCorners + 16];     // the next index in the same cell
     uint32_t hist[SBLOCK / 64][256];           // one histogram per wavefront
@@ -1105,33 +1107,83 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
         const int wu = min((int)sm.wcount, CAPW);   // the window's keys no taken corner blocks
         int pw = 1;
         while (pw < wu) pw <<= 1;
-        for (int k = wu + tid; k < pw; k += SBLOCK) { sm.whi[k] = 0; sm.wlo[k] = 0; }
-        __syncthreads();
-        constexpr int PAIRS = CAPW / 2 / SBLOCK;
+        // Bitonic sort, descending, of pw slots (keys past wu are 0, below
+        // every key): thread tid holds elements 4 tid .. 4 tid + 3 in
+        // registers; the compare-exchanges of stride 1 and 2 stay inside a
+        // thread, those of stride 4 .. 128 go to lane tid ^ (stride / 4) of the
+        // same wavefront, and only those of stride 256 and more pass through
+        // LDS (6 barrier pairs for 2048 keys instead of a barrier per stage).
+        static_assert(CAPW == 4 * SBLOCK, "four window keys per thread");
+        Key kk[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 4 * tid + e;
+            kk[e] = i < wu ? Key{sm.whi[i], sm.wlo[i]} : Key{0, 0};
+        }
+        // element i keeps the larger key of (i, i ^ stride) iff i is the lower
+        // one of a descending block ((i & size) == 0) or the upper one of an
+        // ascending block
+        auto keep = [&](int e, Key o, int stride, int size) {
+            const int i = 4 * tid + e;
+            const bool keep_max = ((i & size) == 0) == ((i & stride) == 0);
+            const bool o_less = key_less(o, kk[e]);
+            if (keep_max != o_less) kk[e] = o;
+        };
         for (int size = 2; size <= pw; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                int lo[PAIRS];
-                Key a[PAIRS], b[PAIRS];
+                if (stride >= 256) {
+                    __syncthreads();                     // the last stage's reads are done
 #pragma unroll
-                for (int i = 0; i < PAIRS; ++i) {
-                    const int k = tid + i * SBLOCK;
-                    lo[i] = 2 * k - (k & (stride - 1));
-                    if (k < pw / 2) {
-                        a[i] = Key{sm.whi[lo[i]], sm.wlo[lo[i]]};
-                        b[i] = Key{sm.whi[lo[i] + stride], sm.wlo[lo[i] + stride]};
+                    for (int e = 0; e < 4; ++e) {
+                        sm.whi[4 * tid + e] = kk[e].hi;
+                        sm.wlo[4 * tid + e] = kk[e].lo;
+                    }
+                    __syncthreads();
+                    Key o[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int j = (4 * tid + e) ^ stride;
+                        o[e] = Key{sm.whi[j], sm.wlo[j]};
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) keep(e, o[e], stride, size);
+                } else if (stride >= 4) {
+                    // all twelve exchanges in flight before the first use
+                    const int m = stride >> 2;
+                    Key o[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        o[e].hi = __shfl_xor(kk[e].hi, m, 64);
+                        o[e].lo = __shfl_xor(kk[e].lo, m, 64);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) keep(e, o[e], stride, size);
+                } else {
+                    // (all four elements share (i & size) for size >= 4)
+                    auto cex = [&](Key &a, Key &b, int i) {
+                        if (key_less(a, b) == ((i & size) == 0)) {
+                            const Key t = a;
+                            a = b;
+                            b = t;
+                        }
+                    };
+                    if (stride == 2) {
+                        cex(kk[0], kk[2], 4 * tid);
+                        cex(kk[1], kk[3], 4 * tid + 1);
+                    } else {
+                        cex(kk[0], kk[1], 4 * tid);
+                        cex(kk[2], kk[3], 4 * tid + 2);
                     }
                 }
-#pragma unroll
-                for (int i = 0; i < PAIRS; ++i) {
-                    const int k = tid + i * SBLOCK;
-                    if (k < pw / 2 && key_less(a[i], b[i]) == ((lo[i] & size) == 0)) {
-                        sm.whi[lo[i]] = b[i].hi; sm.wlo[lo[i]] = b[i].lo;
-                        sm.whi[lo[i] + stride] = a[i].hi; sm.wlo[lo[i] + stride] = a[i].lo;
-                    }
-                }
-                __syncthreads();
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            sm.whi[4 * tid + e] = kk[e].hi;
+            sm.wlo[4 * tid + e] = kk[e].lo;
+        }
+        __syncthreads();
         // ---- accept in rank order, CHUNK candidates at a time
         for (int c0 = 0; c0 < wu && nt < max_corners; c0 += CHUNK) {
             const int k = c0 + tid;
@@ -1175,35 +1227,43 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             }
             at += __popcll(sm.und[wv] & ((1ull << lane) - 1));
             if (!blocked) {
-                sm.cx[at] = x;
-                sm.cy[at] = y;
+                sm.cxy[at] = (uint32_t)x | ((uint32_t)y << 16);
             }
             __syncthreads();
-            // packed candidate t = tid: its conflicts with the better packed
-            // candidates u < t (squared distance < min_dist^2), one 64-bit
-            // mask per group of 64, 8 tests per step
-            const bool live = tid < mu;
-            if (live && spaced) {
-                const int xt = sm.cx[tid], yt = sm.cy[tid];
-                const int4 *x4 = reinterpret_cast<const int4 *>(sm.cx), *y4 = reinterpret_cast<const int4 *>(sm.cy);
+            // conflicts of packed candidate t with the better packed ones
+            // u < t (squared distance < min_dist^2), one 64-bit mask per group
+            // of 64: the triangle's 64 x 64 blocks (row group g, column group
+            // h <= g) are dealt to the wavefronts in turn, a lane per row.
+            // Positions are int16 pairs (coordinates < 32768): one packed
+            // subtract and one 16-bit dot product give dx^2 + dy^2 exactly
+            // (at most 2 * 32767^2 < 2^31).
+            if (spaced) {
+                const int ng = (mu + 63) >> 6;
+                const int nblk = ng * (ng + 1) / 2;
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(sm.cxy);
+                for (int blk = wv; blk < nblk; blk += SBLOCK / 64) {
+                    int g = 0;
+                    while ((g + 1) * (g + 2) / 2 <= blk) ++g;
+                    const int h = blk - g * (g + 1) / 2;
+                    const int t = 64 * g + lane;
+                    if (t < mu) {
+                        const s16x2 pt = __builtin_bit_cast(s16x2, sm.cxy[t]);
+                        const int u_end = h < g ? 64 : lane;    // columns 64 h + [0, u_end)
+                        unsigned long long mw = 0;
+                        for (int i0 = 0; i0 < u_end; i0 += 8) {
+                            const uint4 a = p4[(64 * h + i0) / 4], b = p4[(64 * h + i0) / 4 + 1];
+                            const uint32_t pu[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+                            uint32_t bits = 0;
 #pragma unroll
-                for (int w = 0; w < CHUNK / 64; ++w) {
-                    if (64 * w > tid) break;
-                    unsigned long long mw = 0;
-                    const int u_end = min(tid, 64 * w + 64);
-                    for (int u0 = 64 * w; u0 < u_end; u0 += 8) {
-                        const int4 xa = x4[u0 / 4], xb = x4[u0 / 4 + 1], ya = y4[u0 / 4], yb = y4[u0 / 4 + 1];
-                        const int ux[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-                        const int uy[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
-                        unsigned long long bits = 0;
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int dx = xt - ux[i], dy = yt - uy[i];
-                            bits |= (unsigned long long)((u0 + i < tid) && (dx * dx + dy * dy < md2)) << i;
+                            for (int i = 0; i < 8; ++i) {
+                                const s16x2 d = pt - __builtin_bit_cast(s16x2, pu[i]);
+                                const int dd = __builtin_amdgcn_sdot2(d, d, 0, false);
+                                bits |= (uint32_t)(dd < md2 && i0 + i < u_end) << i;
+                            }
+                            mw |= (unsigned long long)bits << i0;
                         }
-                        mw |= bits << (u0 & 63);
+                        sm.cmask[t][h] = mw;
                     }
-                    sm.cmask[tid][w] = mw;
                 }
             }
             __syncthreads();
@@ -1255,11 +1315,12 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 if (w < wv) before += __popcll(sw);
                 else if (w == wv) before += __popcll(sw & ((1ull << lane) - 1));
             }
-            const bool mine = live && ((sm.sel[wv] >> lane) & 1ull);
+            const bool mine = tid < mu && ((sm.sel[wv] >> lane) & 1ull);
             const int pos = nt + before;
             if (mine && pos < max_corners) {
-                const int xm = sm.cx[tid], ym = sm.cy[tid];
-                sm.taken[pos] = (uint32_t)xm | ((uint32_t)ym << 16);
+                const uint32_t pm = sm.cxy[tid];
+                const int xm = (int)(pm & 0xFFFFu), ym = (int)(pm >> 16);
+                sm.taken[pos] = pm;
                 // into its grid cell's list (corners of one cell may arrive together)
                 sm.tg_next[pos] = atomicExch(&sm.tg_head[(ym / T.cs) * T.gx + xm / T.cs], pos);
             }
