@@ -832,8 +832,9 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_bucket(const GfttJob *__restrict
 
 constexpr int CAPW = kGfttWindow;             // window of peaks sorted in LDS
 constexpr int TG_CELLS = 2048;                // cells of the taken-corner grid, at most
-constexpr int SBLOCK = 512;                   // threads of the selection workgroup
-constexpr int CHUNK = SBLOCK;                 // candidates decided together
+constexpr int SBLOCK = 1024;                  // threads of the selection workgroup
+constexpr int CHUNK = 512;                    // candidates decided together (the first CHUNK threads)
+constexpr int KPT = 4;                        // keys per thread in flight in the list passes
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 struct alignas(16) SelSmem {
@@ -997,15 +998,15 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             for (int d = lz + 8; d < 96; d += 8) {
                 for (int k = tid; k < (SBLOCK / 64) * 256; k += SBLOCK) (&sm.hist[0][0])[k] = 0;
                 __syncthreads();
-                for (int k0 = 0; k0 < nB; k0 += 8 * SBLOCK) {
-                    Key key[8];
+                for (int k0 = 0; k0 < nB; k0 += KPT * SBLOCK) {
+                    Key key[KPT];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) {
+                    for (int i = 0; i < KPT; ++i) {
                         const int k = k0 + i * SBLOCK + tid;
                         key[i] = k < nB ? Key{srcB[k].rbits, ~srcB[k].idx} : Key{0, 0};
                     }
 #pragma unroll
-                    for (int i = 0; i < 8; ++i)
+                    for (int i = 0; i < KPT; ++i)
                         if (key[i].hi != 0 && eligible(key[i], bounded, bound) && key_prefix_eq(key[i], prefix, d))
                             atomicAdd(&sm.hist[wv][key_digit(key[i], d)], 1u);
                 }
@@ -1047,18 +1048,18 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 if (whole) break;
                 if (!filtered && 4 * kept <= nB) {
                     // copy bucket be's eligible keys >= prefix (its lower bytes
-                    // are 0) to the scratch list, 8 keys per thread in flight
+                    // are 0) to the scratch list, KPT keys per thread in flight
                     if (tid == 0) sm.wcount = 0;
                     __syncthreads();
-                    for (int k0 = 0; k0 < nB; k0 += 8 * SBLOCK) {
-                        GfttPeak pk[8];
+                    for (int k0 = 0; k0 < nB; k0 += KPT * SBLOCK) {
+                        GfttPeak pk[KPT];
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) {
+                        for (int i = 0; i < KPT; ++i) {
                             const int k = k0 + i * SBLOCK + tid;
                             pk[i] = k < nB ? srcB[k] : GfttPeak{};
                         }
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) {
+                        for (int i = 0; i < KPT; ++i) {
                             const int k = k0 + i * SBLOCK + tid;
                             const Key key{pk[i].rbits, ~pk[i].idx};
                             const bool take = k < nB && eligible(key, bounded, bound) && !key_less(key, prefix);
@@ -1081,16 +1082,16 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
         __syncthreads();
         const bool screen = spaced && nt > 0;
         const int nA = a_hi - a_lo, ngat = nA + nB;
-        for (int k0 = 0; k0 < ngat; k0 += 8 * SBLOCK) {
-            Key key[8];
+        for (int k0 = 0; k0 < ngat; k0 += KPT * SBLOCK) {
+            Key key[KPT];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < KPT; ++i) {
                 const int k = k0 + i * SBLOCK + tid;
                 const GfttPeak *q = k < nA ? list + a_lo + k : srcB + (k - nA);
                 key[i] = k < ngat ? Key{q->rbits, ~q->idx} : Key{0, 0};
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < KPT; ++i) {
                 bool take = key[i].hi != 0 && eligible(key[i], bounded, bound) && !key_less(key[i], low);
                 if (take && screen) {
                     const int idx = (int)~key[i].lo, yk = idx / W, xk = idx - yk * W;
@@ -1108,58 +1109,60 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
         int pw = 1;
         while (pw < wu) pw <<= 1;
         // Bitonic sort, descending, of pw slots (keys past wu are 0, below
-        // every key): thread tid holds elements 4 tid .. 4 tid + 3 in
-        // registers; the compare-exchanges of stride 1 and 2 stay inside a
-        // thread, those of stride 4 .. 128 go to lane tid ^ (stride / 4) of the
-        // same wavefront, and only those of stride 256 and more pass through
-        // LDS (6 barrier pairs for 2048 keys instead of a barrier per stage).
-        static_assert(CAPW == 4 * SBLOCK, "four window keys per thread");
-        Key kk[4];
+        // every key): thread tid holds elements E tid .. E tid + E - 1 in
+        // registers; the compare-exchanges of stride below E stay inside a
+        // thread, those of stride E .. 32 E go to lane tid ^ (stride / E) of
+        // the same wavefront, and only those of stride 64 E and more pass
+        // through LDS (6 barrier pairs for 2048 keys instead of a barrier per
+        // stage).
+        constexpr int E = CAPW / SBLOCK;
+        static_assert(E == 2 || E == 4, "two or four window keys per thread");
+        Key kk[E];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int i = 4 * tid + e;
+        for (int e = 0; e < E; ++e) {
+            const int i = E * tid + e;
             kk[e] = i < wu ? Key{sm.whi[i], sm.wlo[i]} : Key{0, 0};
         }
         // element i keeps the larger key of (i, i ^ stride) iff i is the lower
         // one of a descending block ((i & size) == 0) or the upper one of an
         // ascending block
         auto keep = [&](int e, Key o, int stride, int size) {
-            const int i = 4 * tid + e;
+            const int i = E * tid + e;
             const bool keep_max = ((i & size) == 0) == ((i & stride) == 0);
             const bool o_less = key_less(o, kk[e]);
             if (keep_max != o_less) kk[e] = o;
         };
         for (int size = 2; size <= pw; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                if (stride >= 256) {
+                if (stride >= 64 * E) {
                     __syncthreads();                     // the last stage's reads are done
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        sm.whi[4 * tid + e] = kk[e].hi;
-                        sm.wlo[4 * tid + e] = kk[e].lo;
+                    for (int e = 0; e < E; ++e) {
+                        sm.whi[E * tid + e] = kk[e].hi;
+                        sm.wlo[E * tid + e] = kk[e].lo;
                     }
                     __syncthreads();
-                    Key o[4];
+                    Key o[E];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int j = (4 * tid + e) ^ stride;
+                    for (int e = 0; e < E; ++e) {
+                        const int j = (E * tid + e) ^ stride;
                         o[e] = Key{sm.whi[j], sm.wlo[j]};
                     }
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) keep(e, o[e], stride, size);
-                } else if (stride >= 4) {
-                    // all twelve exchanges in flight before the first use
-                    const int m = stride >> 2;
-                    Key o[4];
+                    for (int e = 0; e < E; ++e) keep(e, o[e], stride, size);
+                } else if (stride >= E) {
+                    // all exchanges in flight before the first use
+                    const int m = stride / E;
+                    Key o[E];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
+                    for (int e = 0; e < E; ++e) {
                         o[e].hi = __shfl_xor(kk[e].hi, m, 64);
                         o[e].lo = __shfl_xor(kk[e].lo, m, 64);
                     }
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) keep(e, o[e], stride, size);
+                    for (int e = 0; e < E; ++e) keep(e, o[e], stride, size);
                 } else {
-                    // (all four elements share (i & size) for size >= 4)
+                    // inside the thread (the elements of a pair share (i & size))
                     auto cex = [&](Key &a, Key &b, int i) {
                         if (key_less(a, b) == ((i & size) == 0)) {
                             const Key t = a;
@@ -1167,27 +1170,31 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                             b = t;
                         }
                     };
-                    if (stride == 2) {
-                        cex(kk[0], kk[2], 4 * tid);
-                        cex(kk[1], kk[3], 4 * tid + 1);
+                    if constexpr (E == 2) {
+                        cex(kk[0], kk[1], 2 * tid);
                     } else {
-                        cex(kk[0], kk[1], 4 * tid);
-                        cex(kk[2], kk[3], 4 * tid + 2);
+                        if (stride == 2) {
+                            cex(kk[0], kk[2], 4 * tid);
+                            cex(kk[1], kk[3], 4 * tid + 1);
+                        } else {
+                            cex(kk[0], kk[1], 4 * tid);
+                            cex(kk[2], kk[3], 4 * tid + 2);
+                        }
                     }
                 }
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            sm.whi[4 * tid + e] = kk[e].hi;
-            sm.wlo[4 * tid + e] = kk[e].lo;
+        for (int e = 0; e < E; ++e) {
+            sm.whi[E * tid + e] = kk[e].hi;
+            sm.wlo[E * tid + e] = kk[e].lo;
         }
         __syncthreads();
         // ---- accept in rank order, CHUNK candidates at a time
         for (int c0 = 0; c0 < wu && nt < max_corners; c0 += CHUNK) {
             const int k = c0 + tid;
-            const bool valid = k < wu;
+            const bool valid = tid < CHUNK && k < wu;   // the first CHUNK threads hold the chunk
             int x = 0, y = 0;
             bool blocked = !valid;
             if (valid) {
@@ -1215,7 +1222,7 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
             // in rank order at cx / cy [0, mu)
             {
                 const unsigned long long free_bits = __ballot(!blocked);
-                if (lane == 0) sm.und[wv] = free_bits;
+                if (lane == 0 && wv < CHUNK / 64) sm.und[wv] = free_bits;
             }
             __syncthreads();
             int mu = 0, at = 0;
@@ -1225,8 +1232,8 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 mu += c;
                 at += w < wv ? c : 0;
             }
-            at += __popcll(sm.und[wv] & ((1ull << lane) - 1));
             if (!blocked) {
+                at += __popcll(sm.und[wv] & ((1ull << lane) - 1));
                 sm.cxy[at] = (uint32_t)x | ((uint32_t)y << 16);
             }
             __syncthreads();
