@@ -59,12 +59,25 @@ def oracle_corners(im, occ=None, **kw):
                        max_corners=kw.get("max_corners", 200), border=kw.get("border", 0), occupied=occ)
 
 
+# (129, 125): a last row of strips one row tall; (200, 61): a last column of
+# strips one column wide, and strips away from the top and bottom edges
+# (their walk rolls the separable gradient) between strips that touch them
 @pytest.mark.parametrize("r", [0, 1, 2, 3])
-@pytest.mark.parametrize("shape", [(3, 3), (5, 70), (17, 65), (61, 83), (480, 752)])
+@pytest.mark.parametrize("shape", [(3, 3), (5, 70), (17, 65), (61, 83), (129, 125), (200, 61), (480, 752)])
 def test_response_bitwise(det, r, shape):
     im = texture(*shape, 10 + r)
     print("response r=%d shape=%s" % (r, shape), flush=True)
     (_, R), = run(det, [im], r=r, response=True)
+    want = oracle.gftt_response(im, r)
+    assert np.array_equal(R.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("r", [0, 1])
+def test_response_bitwise_unaligned_pitch(det, r):
+    """Rows whose pitch (145 bytes) is no multiple of 8: the staging loads bytes."""
+    im = texture(200, 131, 40 + r)
+    print("response unaligned pitch r=%d" % r, flush=True)
+    (_, R), = run(det, [im], r=r, response=True, pitch_pad=14)
     want = oracle.gftt_response(im, r)
     assert np.array_equal(R.view(np.uint64), want.view(np.uint64))
 
@@ -83,7 +96,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("kw", CASES, ids=[str(i) for i in range(len(CASES))])
-@pytest.mark.parametrize("shape", [(480, 752), (97, 131)])
+@pytest.mark.parametrize("shape", [(480, 752), (97, 131), (200, 61)])
 def test_corners_exact(det, kw, shape):
     im = texture(*shape, 3)
     print("corners %s shape=%s" % (kw, shape), flush=True)
