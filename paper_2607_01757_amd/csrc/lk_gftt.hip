@@ -10,7 +10,7 @@
 //                  counters (a fill kernel, safe under graph capture);
 //   k_gftt_peaks   the response, its 3x3 local maxima with R > 0 appended to
 //                  the frame's peak list, the frame maximum raised with one
-//                  atomic per workgroup: block radius 0 and 1 walk 60x64
+//                  atomic per workgroup: block radius 0 and 1 walk 60x32
 //                  strips with one wavefront each (k_gftt_peaks_strip), radius
 //                  2 and 3 stage 64x16 tiles in LDS;
 //   k_gftt_compact keeps the peaks above the quality threshold that no cached
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
 
 // ---- responses and peaks, block radius 0 and 1: one wavefront per strip ------
 //
-// A strip is 60 output columns x 64 output rows; lane i owns frame column
+// A strip is 60 output columns x 32 output rows; lane i owns frame column
 // X = x0 - 2 + i and walks down the rows.  Per row it forms the Scharr
 // gradient of its column from the staged frame bytes (at the reflect-101
 // position, as the tiled kernel does), the three products, their horizontal

@@ -159,7 +159,7 @@ struct EpiJob {
 };
 
 constexpr int kGfttTileW = 64, kGfttTileH = 16;      // response tiles, block radius 2 and 3
-constexpr int kGfttStripW = 60, kGfttStripH = 64;    // response strips of one wavefront, radius 0 and 1
+constexpr int kGfttStripW = 60, kGfttStripH = 32;    // response strips of one wavefront, radius 0 and 1
 // Response tile (or strip) of a detection with block radius r.
 inline void gftt_tile_shape(int r, int *tw, int *th)
 {
