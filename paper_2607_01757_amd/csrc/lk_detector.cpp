@@ -46,14 +46,19 @@ lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const l
         return fail(LK_ERR_INVALID_ARG, "%d frames exceed the detector's %d", n_frames, det->max_frames);
     if (n_frames == 0) return LK_SUCCESS;
     int64_t pixels = 0;
-    long long tiles = 0;
-    int tw = 0, th = 0;
-    gftt_tile_shape(p->radius, &tw, &th);
     for (int f = 0; f < n_frames; ++f) {
-        GfttJob &J = jobs[f];
+        const GfttJob &J = jobs[f];
         if (J.w < 3 || J.h < 3 || J.w > 32768 || J.h > 32768)
             return fail(LK_ERR_INVALID_ARG, "frame %d: size %dx%d not in [3, 32768]^2", f, J.w, J.h);
         if (J.pitch < J.w) return fail(LK_ERR_INVALID_ARG, "frame %d: pitch < width", f);
+        pixels += (int64_t)J.w * J.h;
+    }
+    long long tiles = 0;
+    int tw = 0, th = 0;
+    gftt_tile_shape(p->radius, pixels, &tw, &th);
+    pixels = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        GfttJob &J = jobs[f];
         J.tiles_x = (J.w + tw - 1) / tw;
         J.tile_begin = (int32_t)tiles;
         J.peaks = det->d_peaks + pixels;
@@ -88,7 +93,7 @@ lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const l
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(detector jobs)");
     e = launch_gftt(static_cast<const GfttJob *>(slot->dev),
                     reinterpret_cast<const int32_t *>(static_cast<const char *>(slot->dev) + jbytes), n_frames,
-                    (int)tiles, p->radius, p->border, p->quality, p->min_dist, p->max_corners, s);
+                    (int)tiles, th, p->radius, p->border, p->quality, p->min_dist, p->max_corners, s);
     (void)hipEventRecord(slot->done, s);
     return e == hipSuccess ? LK_SUCCESS : hip_fail(e, "detector launch");
 }

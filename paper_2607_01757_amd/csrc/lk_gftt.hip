@@ -11,7 +11,8 @@
 //   k_gftt_peaks   the response, its 3x3 local maxima with R > 0 appended to
 //                  the frame's peak list, the frame maximum raised with one
 //                  atomic per workgroup: block radius 0 and 1 walk 60x32
-//                  strips with one wavefront each (k_gftt_peaks_strip), radius
+//                  strips (60x64 in large calls) with one wavefront each
+//                  (k_gftt_peaks_strip), radius
 //                  2 and 3 stage 64x16 tiles in LDS;
 //   k_gftt_compact keeps the peaks above the quality threshold that no cached
 //                  occupied point blocks and counts them by bucket (the first
@@ -276,8 +277,8 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
 
 // ---- responses and peaks, block radius 0 and 1: one wavefront per strip ------
 //
-// A strip is 60 output columns x 32 output rows; lane i owns frame column
-// X = x0 - 2 + i and walks down the rows.  Per row it forms the Scharr
+// A strip is 60 output columns x SH output rows (32, or 64 in large calls);
+// lane i owns frame column X = x0 - 2 + i and walks down the rows.  Per row it forms the Scharr
 // gradient of its column from the staged frame bytes (at the reflect-101
 // position, as the tiled kernel does), the three products, their horizontal
 // (2r+1)-sums over neighbouring lanes by wave-shift DPP, and their vertical
@@ -293,9 +294,9 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
 
 constexpr int kStripWaves = 1;                // strips per workgroup, one per wavefront
 
-template <int R>
+template <int R, int SH>
 struct alignas(16) StripSmem {
-    static constexpr int IH = kGfttStripH + 2 * R + 4, IW = 80;   // frame rows y0-2-R.., columns sx0..
+    static constexpr int IH = SH + 2 * R + 4, IW = 80;            // frame rows y0-2-R.., columns sx0..
     static constexpr int NBUF = 128;
     uint8_t img[IH][IW];
     GfttPeak buf[NBUF];                                           // peaks waiting for a global slot
@@ -346,13 +347,13 @@ __device__ __forceinline__ double max3_lanes(double v)
     return max_r(v, max_r(l, r));
 }
 
-template <int R>
+template <int R, int SH>
 __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const GfttJob *__restrict__ jobs,
                                                                       const int32_t *__restrict__ tile_job,
                                                                       int n_tiles, int border)
 {
     static_assert(R == 0 || R == 1, "block radius 0 or 1");
-    using S = StripSmem<R>;
+    using S = StripSmem<R, SH>;
     __shared__ S sms[kStripWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     S &sm = sms[wv];
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
     const GfttJob J = jobs[__builtin_amdgcn_readfirstlane(tile_job[tile])];
     const int t = tile - J.tile_begin;
     const int W = J.w, H = J.h;
-    const int x0 = (t % J.tiles_x) * kGfttStripW, y0 = (t / J.tiles_x) * kGfttStripH;
+    const int x0 = (t % J.tiles_x) * kGfttStripW, y0 = (t / J.tiles_x) * SH;
     const int sx0 = (x0 - 3) & ~7, sy0 = y0 - 2 - R;
     // 1. frame rows [sy0, sy0 + IH) x columns [sx0, sx0 + 80) as bytes (the
     //    walk reads columns x0 - 3 .. x0 + 62), 8-byte loads; a sample
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
     const int xc = (xslot ? reflect101(X, W) : 0) - sx0;       // staged column of the gradient's centre
     const bool xout = lane >= 2 && lane < 62 && X < W;          // an output column of the strip
     const bool xin = X >= 0 && X < W;
-    const int ye = min(y0 + kGfttStripH, H);                    // output rows y0 .. ye-1
+    const int ye = min(y0 + SH, H);                             // output rows y0 .. ye-1
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, 1>;
     using S2 = std::integral_constant<int, 2>;
@@ -1363,21 +1364,23 @@ __global__ void k_gftt_reset(const GfttJob *__restrict__ jobs)
 
 }  // namespace
 
-hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int radius,
-                       int border, double quality, int min_dist, int max_corners, hipStream_t s)
+hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int tile_h,
+                       int radius, int border, double quality, int min_dist, int max_corners, hipStream_t s)
 {
     if (njobs <= 0) return hipSuccess;
     k_gftt_reset<<<njobs, 256, 0, s>>>(d_jobs);
     // the tile shape of each radius is the host's (gftt_tile_shape)
     switch (radius) {
     case 0:
-        k_gftt_peaks_strip<0><<<(total_tiles + kStripWaves - 1) / kStripWaves, 64 * kStripWaves, 0, s>>>(
-            d_jobs, d_tile_job, total_tiles, border);
+    case 1: {
+        const dim3 grid((total_tiles + kStripWaves - 1) / kStripWaves), block(64 * kStripWaves);
+        const bool tall = tile_h == kGfttStripHTall;
+        if (radius == 0 && tall) k_gftt_peaks_strip<0, kGfttStripHTall><<<grid, block, 0, s>>>(d_jobs, d_tile_job, total_tiles, border);
+        else if (radius == 0) k_gftt_peaks_strip<0, kGfttStripH><<<grid, block, 0, s>>>(d_jobs, d_tile_job, total_tiles, border);
+        else if (tall) k_gftt_peaks_strip<1, kGfttStripHTall><<<grid, block, 0, s>>>(d_jobs, d_tile_job, total_tiles, border);
+        else k_gftt_peaks_strip<1, kGfttStripH><<<grid, block, 0, s>>>(d_jobs, d_tile_job, total_tiles, border);
         break;
-    case 1:
-        k_gftt_peaks_strip<1><<<(total_tiles + kStripWaves - 1) / kStripWaves, 64 * kStripWaves, 0, s>>>(
-            d_jobs, d_tile_job, total_tiles, border);
-        break;
+    }
     case 2: k_gftt_peaks<2><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     default: k_gftt_peaks<3><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     }

@@ -159,12 +159,18 @@ struct EpiJob {
 };
 
 constexpr int kGfttTileW = 64, kGfttTileH = 16;      // response tiles, block radius 2 and 3
-constexpr int kGfttStripW = 60, kGfttStripH = 32;    // response strips of one wavefront, radius 0 and 1
-// Response tile (or strip) of a detection with block radius r.
-inline void gftt_tile_shape(int r, int *tw, int *th)
+// Response strips of one wavefront (block radius 0 and 1): 60 columns, 32
+// rows, or 64 rows for calls of at least kGfttTallPixels level-0 pixels (about
+// two strips per SIMD), where the shorter walks no longer shorten the launch
+// and their extra halo rows cost.
+constexpr int kGfttStripW = 60, kGfttStripH = 32, kGfttStripHTall = 64;
+constexpr int64_t kGfttTallPixels = int64_t(8) << 20;
+// Response tile (or strip) of a detection with block radius r over `pixels`
+// level-0 pixels in all.
+inline void gftt_tile_shape(int r, int64_t pixels, int *tw, int *th)
 {
     *tw = r <= 1 ? kGfttStripW : kGfttTileW;
-    *th = r <= 1 ? kGfttStripH : kGfttTileH;
+    *th = r <= 1 ? (pixels >= kGfttTallPixels ? kGfttStripHTall : kGfttStripH) : kGfttTileH;
 }
 constexpr int kGfttWindow = 2048;             // peaks sorted per selection window
 constexpr int kGfttMaxCorners = LK_GFTT_MAX_CORNERS;
@@ -222,8 +228,8 @@ hipError_t launch_track_persistent(const BatchItem *d_items, int n_items, int to
                                    hipStream_t stream);
 // Detection of every frame in d_jobs (reset, peaks, compaction, bucket layout,
 // selection: five launches).
-hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int radius,
-                       int border, double quality, int min_dist, int max_corners, hipStream_t stream);
+hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njobs, int total_tiles, int tile_h,
+                       int radius, int border, double quality, int min_dist, int max_corners, hipStream_t stream);
 // Track-pool lifecycle kernels (lk_pool_kernels.hip), one workgroup per stream.
 hipError_t launch_pool_carry(const PoolJob *d_jobs, int n, hipStream_t stream);
 hipError_t launch_pool_append(const PoolJob *d_jobs, int n, hipStream_t stream);

@@ -73,6 +73,34 @@ def test_response_bitwise(det, r, shape):
 
 
 @pytest.mark.parametrize("r", [0, 1])
+def test_tall_strips_of_a_large_call(det, r):
+    """A call of at least 8 Mi pixels walks 64-row strips (smaller calls 32):
+    responses of two of its frames bit for bit, corners of all five exact."""
+    shapes = [(1080, 1920)] * 4 + [(480, 752)]
+    assert sum(h * w for h, w in shapes) >= 8 << 20
+    imgs = [texture(h, w, 60 + 7 * r + i) for i, (h, w) in enumerate(shapes)]
+    print("tall strips r=%d" % r, flush=True)
+    kw = dict(r=r, quality=0.01, min_dist=30, max_corners=200)
+    frames, outs = [], []
+    for k, im in enumerate(imgs):
+        h, w = im.shape
+        f = {"img": torch.from_numpy(im).cuda(),
+             "out_xy": torch.full((200, 2), -1.0, dtype=torch.float32, device="cuda"),
+             "count": torch.full((1,), -1, dtype=torch.int32, device="cuda")}
+        if k in (0, 4):
+            f["response"] = torch.empty((h, w), dtype=torch.float64, device="cuda")
+        frames.append(f)
+    lk.lk_detect_corners(det, frames, lk.gftt_params(r, 30, 200, 0, 0.01))
+    torch.cuda.synchronize()
+    for k, (im, f) in enumerate(zip(imgs, frames)):
+        if "response" in f:
+            want = oracle.gftt_response(im, r)
+            assert np.array_equal(f["response"].cpu().numpy().view(np.uint64), want.view(np.uint64)), k
+        n = int(f["count"].item())
+        assert np.array_equal(f["out_xy"][:n].cpu().numpy(), oracle_corners(im, **kw)), k
+
+
+@pytest.mark.parametrize("r", [0, 1])
 def test_response_bitwise_unaligned_pitch(det, r):
     """Rows whose pitch (145 bytes) is no multiple of 8: the staging loads bytes."""
     im = texture(200, 131, 40 + r)
