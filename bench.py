@@ -246,6 +246,17 @@ def profiled_traffic(kernel, summary="profiles/hbm_counters_batched64.txt",
     return None
 
 
+def detect_traffic():
+    """HBM bytes of one 64-frame detection step: the sum over its kernels of
+    the copy-calibrated counter summary, or None when a kernel is missing
+    from it or the detector source has changed since (the reset kernel, a
+    fill of 2 KiB per frame, is left out)."""
+    parts = [profiled_traffic(k, summary="profiles/hbm_counters_detect64.txt",
+                              source="paper_2607_01757_amd/csrc/lk_gftt.hip")
+             for k in ("k_gftt_peaks_strip", "k_gftt_compact", "k_gftt_bucket", "k_gftt_select")]
+    return None if any(v is None for v in parts) else sum(parts)
+
+
 def cpu_baseline(streams, n_sample, win, levels, fb, n_sample_1t=16):
     """The FP64 oracle timed on the host: on every core over n_sample streams,
     and on one thread over the first n_sample_1t of them."""
@@ -885,7 +896,7 @@ def run_detect(args):
         "topup": res["topup"], "p50_frame_ms": percentile(lat, 50), "p99_frame_ms": percentile(lat, 99),
         "roofline": {"bound": "alu", "kernel": "detection step (reset, peaks, compaction, buckets, selection)",
                      "achieved": ops / t / 1e12, "peak": peak_lane_ops, "unit": "T VALU lane-ops/s",
-                     "frac": ops / t / 1e12 / peak_lane_ops, "traffic": None},
+                     "frac": ops / t / 1e12 / peak_lane_ops, "traffic": detect_traffic()},
     }
     if not args.no_cpu_baseline:
         sample = streams[:8]
