@@ -423,8 +423,13 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
     // gx = 3 d(j-1) + 10 d(j) + 3 d(j+1) and gy = s(j+1) - s(j-1), and each
     // gradient row reads one new staged row.  Elsewhere each gradient row
     // reads its 3x3 taps at the reflect-101 row.
-    auto walk = [&](auto roll_tag) {
+    auto walk = [&](auto roll_tag, auto inside_tag) {
         constexpr bool ROLL = decltype(roll_tag)::value;
+        // INSIDE: every lane's column lies in the frame (strips away from the
+        // left and right edges), so no lane needs a column test
+        constexpr bool INSIDE = decltype(inside_tag)::value;
+        const bool xs = INSIDE || xslot, xi = INSIDE || xin;
+        const bool xo = INSIDE ? (lane >= 2 && lane < 62) : xout;
         int32_t hxx[3] = {0, 0, 0}, hxy[3] = {0, 0, 0}, hyy[3] = {0, 0, 0};   // products of gradient rows
         int32_t hd[3] = {0, 0, 0}, hs[3] = {0, 0, 0};          // d and s of three staged rows (ROLL)
         auto row_taps = [&](int j, int32_t &d, int32_t &sj) {
@@ -440,7 +445,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
             constexpr int P = R == 1 ? N : 0;
             int32_t pxx = 0, pxy = 0, pyy = 0;
             if constexpr (ROLL) {
-                if (xslot) {
+                if (xs) {
                     row_taps(Yg - sy0 + 1, hd[N], hs[N]);
                     const int gx = mad_i24(3, hd[O] + hd[N], mul_i24(10, hd[M]));
                     const int gy = hs[N] - hs[O];
@@ -449,7 +454,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
                     pyy = mul_i24(gy, gy);
                 }
             } else {
-                if (xslot && Yg >= -1 - R && Yg < H + R) {
+                if (xs && Yg >= -1 - R && Yg < H + R) {
                     const int yc = reflect101(Yg, H) - sy0;
                     const int a00 = sm.img[yc - 1][xc - 1], a01 = sm.img[yc - 1][xc], a02 = sm.img[yc - 1][xc + 1];
                     const int a10 = sm.img[yc][xc - 1], a12 = sm.img[yc][xc + 1];
@@ -481,7 +486,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
             // the first gradient row (y0 - 1 - R, staged row 1) has ring slot
             // O = 1 (R = 1) or 0 (R = 0): its staged rows 0 and 1 first
             constexpr int O0 = R == 1 ? 1 : 0;
-            if (xslot) {
+            if (xs) {
                 row_taps(0, hd[O0], hs[O0]);
                 row_taps(1, hd[(O0 + 1) % 3], hs[(O0 + 1) % 3]);
             }
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
             constexpr int Ws = decltype(w_slot)::value, Ps = decltype(p_slot)::value;
             grad_row(w_slot, Yr + R);                           // product slot Ps (R = 1)
             double v = -__builtin_inf();
-            if (xin && Yr >= 0 && Yr < H) {
+            if (xi && (ROLL || (Yr >= 0 && Yr < H))) {         // (every row of a rolling walk is in the frame)
                 const int32_t a = R == 1 ? hxx[0] + hxx[1] + hxx[2] : hxx[0];
                 const int32_t b = R == 1 ? hxy[0] + hxy[1] + hxy[2] : hxy[0];
                 const int32_t c = R == 1 ? hyy[0] + hyy[1] + hyy[2] : hyy[0];
@@ -507,9 +512,9 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
                 const int Yo = Yr - 1;
                 const double r = rr[Ps];
                 bool peak = false;
-                if (xout) {
+                if (xo) {
                     if (J.response) J.response[(size_t)Yo * W + X] = r;
-                    if (r > vmax) vmax = r;
+                    vmax = max_r(vmax, r);                      // (never NaN, never -0)
                     const double mx = max_r(mm[0], max_r(mm[1], mm[2]));
                     peak = r > 0.0 && r == mx && X >= border && Yo >= border && X < W - border && Yo < H - border;
                 }
@@ -520,7 +525,10 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
                         pk.rbits = (unsigned long long)__double_as_longlong(r);
                         pk.idx = (uint32_t)(Yo * W + X);
                         pk.pad = 0;
-                        sm.buf[nbuf + (uint32_t)__popcll(bal & ((1ull << lane) - 1))] = pk;
+                        // the lane's rank among the row's peaks
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        sm.buf[nbuf + rank] = pk;
                     }
                     nbuf += (uint32_t)__popcll(bal);
                     if (nbuf > S::NBUF - 64) flush();           // a full row must still fit
@@ -539,11 +547,15 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_gftt_peaks_strip(const Gft
             if (Yr + 3 > ye) break;
         }
     };
-    // gradient rows y0 - 1 - R .. ye + R
-    if (y0 - 1 - R >= 0 && ye + R <= H - 1)
-        walk(std::true_type{});
+    // gradient rows y0 - 1 - R .. ye + R; lane columns x0 - 2 .. x0 + 61
+    const bool rolls = y0 - 1 - R >= 0 && ye + R <= H - 1;
+    const bool inside = x0 - 2 >= 0 && x0 + 61 < W;
+    if (rolls && inside)
+        walk(std::true_type{}, std::true_type{});
+    else if (rolls)
+        walk(std::true_type{}, std::false_type{});
     else
-        walk(std::false_type{});
+        walk(std::false_type{}, std::false_type{});
     // the rest of the peaks, and the strip's maximum (one atomic each)
     {
         if (nbuf) flush();
