@@ -28,6 +28,7 @@
 //                  exactly (a candidate is taken iff no better candidate that
 //                  is taken lies too close).
 #include "lk_internal.h"
+#include "lk_key.h"
 
 namespace lkmi {
 
@@ -80,47 +81,6 @@ __device__ __forceinline__ double min_eig(int32_t a, int32_t b, int32_t c)
     const double s = sqrt_ge1(disc);
     const double tr = (double)(a + c);
     return (tr - s) * 0.5;
-}
-
-// The rank key of a candidate: 96 bits, R bits then the complemented raster
-// index (larger = earlier), so the order is total.  Digits are 8-bit fields
-// at any bit position p (0 = the most significant bit), read from the key
-// aligned to the top of 128 bits.
-struct Key {
-    unsigned long long hi;   // bits of R (R > 0, so the bits order like R)
-    uint32_t lo;             // complemented raster index
-};
-
-__device__ __forceinline__ bool key_less(Key a, Key b)
-{
-    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
-}
-
-__device__ __forceinline__ unsigned __int128 key_top(Key k)
-{
-    return ((unsigned __int128)k.hi << 64) | ((unsigned __int128)k.lo << 32);
-}
-
-// bits [p, p + 8) of the key, 0 <= p < 96 (bits past the key read as 0)
-__device__ __forceinline__ uint32_t key_digit(Key k, int p)
-{
-    return (uint32_t)((key_top(k) << p) >> 120);
-}
-
-// the leading p bits of k and q agree, 0 <= p <= 96
-__device__ __forceinline__ bool key_prefix_eq(Key k, Key q, int p)
-{
-    return p == 0 || ((key_top(k) ^ key_top(q)) >> (128 - p)) == 0;
-}
-
-// q's leading p bits, then digit v, then zeros: the least key whose digit at
-// p is v among those with q's leading p bits, 0 <= p < 96
-__device__ __forceinline__ Key key_with_digit(Key q, int p, uint32_t v)
-{
-    unsigned __int128 t = key_top(q);
-    t = p == 0 ? (unsigned __int128)0 : (t >> (128 - p)) << (128 - p);
-    t |= (unsigned __int128)(v & 0xFFu) << (120 - p);
-    return Key{(unsigned long long)(t >> 64), (uint32_t)(t >> 32)};
 }
 
 template <int R>
