@@ -238,12 +238,12 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_peaks(const GfttJob *__restrict_
 // ---- responses and peaks, block radius 0 and 1: one wavefront per strip ------
 //
 // A strip is 60 output columns x SH output rows (32, or 64 in large calls);
-// lane i owns frame column X = x0 - 2 + i and walks down the rows.  Per row it forms the Scharr
-// gradient of its column from the staged frame bytes (at the reflect-101
-// position, as the tiled kernel does), the three products, their horizontal
-// (2r+1)-sums over neighbouring lanes by wave-shift DPP, and their vertical
-// sums over the last 2r+1 rows in registers; the response follows from the
-// sums as in the tiled kernel.  Non-maximum suppression is separable: the
+// lane i owns frame column X = x0 - 2 + i and walks down the rows.  Per row
+// it forms the Scharr gradient of its column from the staged frame bytes (at
+// the reflect-101 position, as the tiled kernel does), the three products,
+// their horizontal (2r+1)-sums over neighbouring lanes by wave-shift DPP, and
+// their vertical sums over the last 2r+1 rows in registers; the response
+// follows from the sums as in the tiled kernel.  Non-maximum suppression is separable: the
 // maximum over a 3x3 block is the maximum of three row maxima, each the
 // maximum of a lane and its two neighbours (again by wave shifts), and a
 // response is a local maximum iff it equals that maximum (no response is
