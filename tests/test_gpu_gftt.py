@@ -169,10 +169,28 @@ def test_ties_and_plateaus(det):
     im = np.where(((x // 4) + (y // 4)) % 2 == 0, 40, 210).astype(np.uint8)
     for kw in (dict(r=1, quality=0.01, min_dist=3, max_corners=4096),
                dict(r=2, quality=0.5, min_dist=0, max_corners=4096),
-               dict(r=1, quality=0.01, min_dist=9, max_corners=37)):
+               dict(r=1, quality=0.01, min_dist=9, max_corners=37),
+               # a threshold a few ulps below the maximum: the candidates are
+               # the maxima, their R bits agree with the threshold's in all
+               # but the last few, so their bucket is made of the last R bits
+               # and the first bits of the index
+               dict(r=1, quality=1.0 - 2.0 ** -50, min_dist=3, max_corners=4096),
+               dict(r=1, quality=1.0 - 2.0 ** -50, min_dist=0, max_corners=25)):
         (got, _), = run(det, [im], **kw)
         want = oracle_corners(im, **kw)
-        assert np.array_equal(got, want), kw
+        assert len(want) > 0 and np.array_equal(got, want), kw
+
+
+def test_threshold_an_ulp_below_the_maximum(det):
+    """quality 1 - 2^-50 on textured frames: the threshold's R bits agree
+    with the maximum's in their first 59-61 bits, so the candidates' bucket
+    straddles the R bits and the index bits of the rank key."""
+    imgs = [texture(97, 131, 70 + k) for k in range(5)]
+    kw = dict(r=1, quality=1.0 - 2.0 ** -50, min_dist=0, max_corners=10)
+    outs = run(det, imgs, **kw)
+    for im, (got, _) in zip(imgs, outs):
+        want = oracle_corners(im, **kw)
+        assert len(want) >= 1 and np.array_equal(got, want)
 
 
 def test_flat_and_tiny_frames(det):
