@@ -300,10 +300,10 @@ lk_result lk_exec_table_lookup(lk_context *ctx, const lk_batch_desc *desc, lk_ex
  *      lies at squared distance < min_dist^2 (occupied points at binary64
  *      distance from the integer pixel), until max_corners are accepted.
  * A detector owns a device workspace for up to max_frames frames and
- * max_pixels pixels per call (32 bytes per pixel plus 2064 per frame); calls
- * on one detector share it, so they must be ordered on one stream (or by the
- * caller).  lk_detect_corners only enqueues work (one small table copy and
- * five launches). */
+ * max_pixels pixels per call (32.125 bytes per pixel plus 2080 per frame);
+ * calls on one detector share it, so they must be ordered on one stream (or
+ * by the caller).  lk_detect_corners only enqueues work (one small table copy
+ * and five launches). */
 #define LK_GFTT_MAX_CORNERS 4096
 
 typedef struct {

@@ -21,6 +21,7 @@ struct lk_detector {
     uint32_t *d_hist = nullptr;      // 256 bins, then 256 bucket counters, per frame
     GfttPeak *d_peaks = nullptr;
     GfttPeak *d_cand = nullptr;
+    uint32_t *d_keep = nullptr;      // 1 bit per peak
 };
 
 namespace lkmi {
@@ -54,6 +55,7 @@ lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const l
         pixels += (int64_t)J.w * J.h;
     }
     long long tiles = 0;
+    int64_t keep_words = 0;
     int tw = 0, th = 0;
     gftt_tile_shape(p->radius, pixels, &tw, &th);
     pixels = 0;
@@ -68,6 +70,8 @@ lk_result detector_enqueue(lk_detector *det, std::vector<GfttJob> &jobs, const l
         J.max_bits = det->d_max + f;
         J.hist = det->d_hist + 512 * (size_t)f;
         J.cursor = J.hist + 256;
+        J.keep = det->d_keep + keep_words;
+        keep_words += ((int64_t)J.w * J.h + 63) / 64 * 2 + 2;
         pixels += (int64_t)J.w * J.h;
         tiles += (long long)J.tiles_x * ((J.h + th - 1) / th);
     }
@@ -115,7 +119,8 @@ lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pi
     const size_t hist_bytes = (size_t)max_frames * 512 * sizeof(uint32_t);
     const size_t peaks_off = hist_off + hist_bytes;
     const size_t cand_off = peaks_off + (size_t)max_pixels * sizeof(GfttPeak);
-    const size_t bytes = cand_off + (size_t)max_pixels * sizeof(GfttPeak);
+    const size_t keep_off = cand_off + (size_t)max_pixels * sizeof(GfttPeak);
+    const size_t bytes = keep_off + ((size_t)max_pixels / 32 + 4 * (size_t)max_frames + 64) * sizeof(uint32_t);
     if (ctx->budget && ctx->in_use.load() + bytes > ctx->budget)
         return fail(LK_ERR_OUT_OF_MEMORY, "detector workspace of %zu bytes exceeds the context budget", bytes);
     lk_detector *d = new (std::nothrow) lk_detector();
@@ -132,6 +137,7 @@ lk_result lk_detector_create(lk_context *ctx, int32_t max_frames, int64_t max_pi
     d->d_hist = reinterpret_cast<uint32_t *>(static_cast<char *>(d->d_ws) + hist_off);
     d->d_peaks = reinterpret_cast<GfttPeak *>(static_cast<char *>(d->d_ws) + peaks_off);
     d->d_cand = reinterpret_cast<GfttPeak *>(static_cast<char *>(d->d_ws) + cand_off);
+    d->d_keep = reinterpret_cast<uint32_t *>(static_cast<char *>(d->d_ws) + keep_off);
     ctx->in_use += bytes;
     *out = d;
     return LK_SUCCESS;

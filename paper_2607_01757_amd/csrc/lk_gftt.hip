@@ -12,12 +12,14 @@
 //                  the frame's peak list, the frame maximum raised with one
 //                  atomic per workgroup: block radius 0 and 1 walk 60x32
 //                  strips (60x64 in large calls) with one wavefront each
-//                  (k_gftt_peaks_strip), radius
-//                  2 and 3 stage 64x16 tiles in LDS;
-//   k_gftt_compact keeps the peaks above the quality threshold that no cached
-//                  occupied point blocks and counts them by bucket (the first
-//                  byte of their R bits that the threshold leaves open);
-//   k_gftt_bucket  lays the candidates out by bucket, best first;
+//                  (k_gftt_peaks_strip), radius 2 and 3 stage 64x16 tiles
+//                  in LDS;
+//   k_gftt_compact counts the peaks above the quality threshold that no
+//                  cached occupied point blocks, in all and by bucket (the 8
+//                  key bits after those the threshold and the maximum share),
+//                  and marks them (one bit each) or, with occupied points,
+//                  appends them to the candidate list;
+//   k_gftt_bucket  writes them by bucket, best first;
 //   k_gftt_select  one workgroup per frame: windows of the best remaining
 //                  candidates are found from the bucket counts and, inside
 //                  the last bucket a window reaches, by radix selection on the
@@ -647,6 +649,17 @@ __device__ __forceinline__ bool occ_grid_blocked(const OccGrid &G, const OccGrid
     return blocked;
 }
 
+// The occupied points of a frame (read on the device where the count is),
+// and whether the compaction filters by them; the same for every thread.
+__device__ __forceinline__ int gftt_n_occupied(const GfttJob &J)
+{
+    return __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
+}
+__device__ __forceinline__ bool gftt_filtered(const GfttJob &J, int min_dist)
+{
+    return gftt_n_occupied(J) > 0 && min_dist > 0;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restrict__ jobs, double quality,
                                                        int min_dist)
 {
@@ -660,8 +673,8 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
     const int np = *J.n_peaks;
     // peaks that a cached occupied point blocks can never be selected: they
     // are dropped here (the selection still checks every occupied point)
-    const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
-    const bool filter = n_occ > 0 && min_dist > 0;
+    const int n_occ = gftt_n_occupied(J);
+    const bool filter = gftt_filtered(J, min_dist);
     OccGrid G{1, 1, 1, 0};
     if (filter) G = occ_grid_build<BLOCK>(J, n_occ, min_dist, s_grid);
     const double md2d = (double)min_dist * (double)min_dist;
@@ -680,13 +693,18 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
     const unsigned long long diff = max_bits ^ thr_bits;
     const int lz = diff ? __clzll((long long)diff) : 64;
     __syncthreads();                           // s_hist is cleared (when no grid was built)
-    // this workgroup's slice of the frame's peaks, read once, CB per thread
-    // at a time; each batch's kept peaks get one range of the candidate list
-    // (one global atomic), wavefronts in turn, lanes by their ballot prefix
-    // (the order does not matter: the selection ranks by the total key)
-    const int per = (np + gridDim.x - 1) / gridDim.x;
+    // this workgroup's slice of the frame's peaks (a multiple of 64 long),
+    // CB per thread at a time: the kept ones counted by bucket.  Without
+    // occupied points they are marked in the keep bits (a wavefront's 64
+    // consecutive peaks are two words; the words of a slice are its
+    // workgroup's alone) and counted in all; with them (most peaks blocked)
+    // each batch's kept peaks get one range of the candidate list (one global
+    // atomic), wavefronts in turn, lanes by their ballot prefix (the order
+    // does not matter: the selection ranks by the total key)
+    const int per = ((np + gridDim.x - 1) / gridDim.x + 63) & ~63;
     const int k_lo = min(np, (int)blockIdx.x * per), k_hi = min(np, k_lo + per);
     constexpr int CB = 8;
+    uint32_t mine = 0;                         // the wavefront's kept peaks (keep-bit form)
     for (int k0 = k_lo; k0 < k_hi; k0 += CB * BLOCK) {
         GfttPeak p[CB];
         unsigned long long m[CB];
@@ -703,6 +721,15 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
             if (keep && lz < 64) atomicAdd(&s_hist[key_digit(Key{p[i].rbits, ~p[i].idx}, lz)], 1u);
             m[i] = __ballot(keep);
             wc += (uint32_t)__popcll(m[i]);
+            const int base = k0 + i * BLOCK + 64 * wv;           // the wavefront's first peak
+            if (!filter && lane == 0 && base < k_hi) {
+                J.keep[base >> 5] = (uint32_t)m[i];
+                J.keep[(base >> 5) + 1] = (uint32_t)(m[i] >> 32);
+            }
+        }
+        if (!filter) {
+            mine += wc;
+            continue;
         }
         if (lane == 0) s_cnt[wv] = wc;
         __syncthreads();
@@ -724,24 +751,41 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_compact(const GfttJob *__restric
         }
         __syncthreads();                       // s_cnt and s_base are reused
     }
+    if (!filter) {
+        // workgroup total of the keep-bit form, one global atomic
+        if (lane == 0) s_cnt[wv] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < BLOCK / 64; ++w) tot += s_cnt[w];
+            if (tot) atomicAdd(J.n_cand, (int)tot);
+        }
+    }
     if (lz < 64 && s_hist[threadIdx.x]) atomicAdd(&J.hist[threadIdx.x], s_hist[threadIdx.x]);
 }
 
 // ---- candidates by bucket -----------------------------------------------------
 //
-// A candidate's bucket is the byte of its R bits that the compaction
-// histogrammed.  This grid (gridDim.x workgroups per frame) lays the frame's
-// candidates out in the peak list by bucket, larger buckets first (in any
-// order within a bucket): every bucket, and every run of buckets, is then one
-// contiguous range, and the selection reads only the buckets a window can
-// reach instead of every candidate.
-__global__ __launch_bounds__(BLOCK) void k_gftt_bucket(const GfttJob *__restrict__ jobs, double quality)
+// A candidate's bucket is the 8 bits of its rank key that the compaction
+// histogrammed.  This grid (gridDim.x workgroups per frame) writes the
+// candidates by bucket, larger buckets first (in any order within a bucket),
+// to the list the selection reads: every bucket, and every run of buckets, is
+// then one contiguous range, and the selection reads only the buckets a
+// window can reach instead of every candidate.  Without occupied points the
+// candidates are the peaks the keep bits mark and go to the candidate list;
+// with them they are the appended candidate list and go to the peak list.
+__global__ __launch_bounds__(BLOCK) void k_gftt_bucket(const GfttJob *__restrict__ jobs, double quality,
+                                                      int min_dist)
 {
     __shared__ uint32_t s_pos[256], s_cnt[256], s_wsum[BLOCK / 64];
     const GfttJob &J = jobs[blockIdx.y];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nc = *J.n_cand;
-    if (nc == 0) return;                       // (then the bucket byte may not exist)
+    if (nc == 0) return;                       // (then the bucket bits may not exist)
+    const bool filter = gftt_filtered(J, min_dist);
+    const GfttPeak *src = filter ? J.cand : J.peaks;
+    GfttPeak *dst = filter ? J.peaks : J.cand;
+    const int np = filter ? nc : *J.n_peaks;
     const unsigned long long max_bits = *J.max_bits;
     const unsigned long long thr_bits =
         (unsigned long long)__double_as_longlong(quality * __longlong_as_double((long long)max_bits));
@@ -761,25 +805,31 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_bucket(const GfttJob *__restrict
     __syncthreads();
     uint32_t start = incl - h;
     for (int w = 0; w < wv; ++w) start += s_wsum[w];
-    // this workgroup's slice, read once, CB per thread at a time: counted by
-    // bucket, a range of each bucket reserved (one global atomic per bucket
-    // the batch holds), then written
-    const int per = (nc + gridDim.x - 1) / gridDim.x;
-    const int k_lo = min(nc, (int)blockIdx.x * per), k_hi = min(nc, k_lo + per);
+    // this workgroup's slice of the peaks, read once, CB per thread at a
+    // time: the kept ones counted by bucket, a range of each bucket reserved
+    // (one global atomic per bucket the batch holds), then written
+    const int per = ((np + gridDim.x - 1) / gridDim.x + 63) & ~63;
+    const int k_lo = min(np, (int)blockIdx.x * per), k_hi = min(np, k_lo + per);
     constexpr int CB = 8;
     for (int k0 = k_lo; k0 < k_hi; k0 += CB * BLOCK) {
         GfttPeak p[CB];
         uint32_t d[CB];
+        bool keep[CB];
+        // the keep bits first: only the kept peaks are read
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
             const int k = k0 + i * BLOCK + tid;
-            p[i] = k < k_hi ? J.cand[k] : GfttPeak{};
+            keep[i] = k < k_hi && (filter || ((J.keep[k >> 5] >> (k & 31)) & 1u));
         }
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
             const int k = k0 + i * BLOCK + tid;
+            p[i] = keep[i] ? src[k] : GfttPeak{};
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
             d[i] = key_digit(Key{p[i].rbits, ~p[i].idx}, lz);
-            if (k < k_hi) atomicAdd(&s_cnt[d[i]], 1u);
+            if (keep[i]) atomicAdd(&s_cnt[d[i]], 1u);
         }
         __syncthreads();
         {
@@ -791,10 +841,8 @@ __global__ __launch_bounds__(BLOCK) void k_gftt_bucket(const GfttJob *__restrict
         s_cnt[tid] = 0u;
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < CB; ++i) {
-            const int k = k0 + i * BLOCK + tid;
-            if (k < k_hi) J.peaks[s_pos[d[i]] + atomicAdd(&s_cnt[d[i]], 1u)] = p[i];
-        }
+        for (int i = 0; i < CB; ++i)
+            if (keep[i]) dst[s_pos[d[i]] + atomicAdd(&s_cnt[d[i]], 1u)] = p[i];
         __syncthreads();
         s_cnt[tid] = 0u;                       // (read by no thread before the next barrier)
         __syncthreads();
@@ -898,8 +946,12 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
     const int md2 = min_dist * min_dist;
     const double md2d = (double)md2;
     const bool spaced = min_dist >= 2;         // distinct pixels are always >= 1 apart
-    const GfttPeak *list = J.peaks;           // the candidates by bucket
-    const int n_occ = __builtin_amdgcn_readfirstlane(J.n_occupied_dev ? *J.n_occupied_dev : J.n_occupied);
+    // the candidates by bucket (the bucket layout's list), and the other
+    // list, free now, for short copies
+    const bool occ_filtered = gftt_filtered(J, min_dist);
+    const GfttPeak *list = occ_filtered ? J.peaks : J.cand;
+    GfttPeak *spare = occ_filtered ? J.cand : J.peaks;
+    const int n_occ = gftt_n_occupied(J);
     // every candidate's R bits lie in (thr_bits, max_bits] (the threshold is
     // formed as the compaction forms it)
     const unsigned long long max_bits = *J.max_bits;
@@ -1021,7 +1073,7 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                 if (whole) break;
                 if (!filtered && 4 * kept <= nB) {
                     // copy bucket be's eligible keys >= prefix (its lower bytes
-                    // are 0) to the scratch list, KPT keys per thread in flight
+                    // are 0) to the spare list, KPT keys per thread in flight
                     if (tid == 0) sm.wcount = 0;
                     __syncthreads();
                     for (int k0 = 0; k0 < nB; k0 += KPT * SBLOCK) {
@@ -1037,11 +1089,11 @@ __global__ __launch_bounds__(SBLOCK) void k_gftt_select(const GfttJob *__restric
                             const Key key{pk[i].rbits, ~pk[i].idx};
                             const bool take = k < nB && eligible(key, bounded, bound) && !key_less(key, prefix);
                             const uint32_t at = wave_append(take, &sm.wcount);
-                            if (take) J.cand[at] = pk[i];
+                            if (take) spare[at] = pk[i];
                         }
                     }
                     __syncthreads();             // the copy is visible to the whole workgroup
-                    srcB = J.cand;
+                    srcB = spare;
                     nB = (int)sm.wcount;
                     filtered = true;
                     __syncthreads();
@@ -1357,7 +1409,7 @@ hipError_t launch_gftt(const GfttJob *d_jobs, const int32_t *d_tile_job, int njo
     default: k_gftt_peaks<3><<<total_tiles, BLOCK, 0, s>>>(d_jobs, d_tile_job, border); break;
     }
     k_gftt_compact<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality, min_dist);
-    k_gftt_bucket<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality);
+    k_gftt_bucket<<<dim3(kCompactBlocks, njobs), BLOCK, 0, s>>>(d_jobs, quality, min_dist);
     k_gftt_select<<<njobs, SBLOCK, 0, s>>>(d_jobs, quality, min_dist, max_corners);
     return hipGetLastError();
 }

@@ -107,14 +107,19 @@ struct GfttJob {
     int32_t n_occupied;
     const float *occupied;
     const int32_t *n_occupied_dev;   // nullable: the number of occupied points, read on the device
-    GfttPeak *peaks;                 // local maxima with R > 0, then the candidates by bucket; capacity w * h
+    GfttPeak *peaks;                 // local maxima with R > 0; capacity w * h
     int32_t *n_peaks;
-    GfttPeak *cand;                  // those above the quality threshold, then the selection's scratch;
-    int32_t *n_cand;                 // capacity w * h
+    GfttPeak *cand;                  // capacity w * h; n_cand: the peaks above the quality threshold that no
+    int32_t *n_cand;                 // occupied point blocks.  With occupied points the compaction appends
+                                     // them to cand and the bucket layout writes them to peaks; without, the
+                                     // bucket layout writes the marked peaks to cand.  The selection reads the
+                                     // bucket layout's list and uses the other as scratch.
     unsigned long long *max_bits;    // bits of max(0, max R)
     uint32_t *hist;                  // 256 bins: the candidates by the first byte of their R bits that the
                                      // threshold and the maximum leave open (their bucket; the compaction's)
     uint32_t *cursor;                // 256 fill counters of the buckets (the bucket layout's)
+    uint32_t *keep;                  // 1 bit per peak: kept by the compaction's test (written by the
+                                     // compaction, 64 peaks per wavefront store; capacity w h / 32 + 4)
     float *out_xy;
     int32_t *count;
     double *response;                // nullable
