@@ -213,6 +213,29 @@ def test_occupied_points(det):
         assert np.array_equal(got, want), n
 
 
+def test_occupied_points_short_distances_and_full_cover(det):
+    """Frames with occupied points (which the compaction filters by) beside
+    frames without (which it marks in keep bits) in one call: occupied points
+    with min_dist 0 (they block nothing), 1 and 5, and a 6-pixel grid of them
+    that at min_dist 5 blocks every peak (no candidate is left)."""
+    shapes = [(97, 131), (97, 131), (97, 131), (120, 90)]
+    imgs = [texture(h, w, 60 + i) for i, (h, w) in enumerate(shapes)]
+    rng = np.random.default_rng(7)
+    scatter = np.column_stack([rng.uniform(-3, 134, 200), rng.uniform(-3, 100, 200)]).astype(np.float32)
+    gx, gy = np.meshgrid(np.arange(0, 137, 6), np.arange(0, 103, 6))   # past the edges too
+    cover = np.column_stack([gx.ravel(), gy.ravel()]).astype(np.float32)
+    occ = [scatter, cover, None, scatter[:50]]
+    for md in (0, 1, 5):
+        kw = dict(r=1, quality=0.001, min_dist=md, max_corners=500)
+        print("occupied short distances min_dist=%d" % md, flush=True)
+        outs = run(det, imgs, occupied=occ, **kw)
+        for k, (im, o, (got, _)) in enumerate(zip(imgs, occ, outs)):
+            want = oracle_corners(im, occ=o, **kw)
+            assert np.array_equal(got, want), (md, k)
+        if md == 5:
+            assert len(outs[1][0]) == 0
+
+
 def test_batched_frames_of_mixed_sizes(det):
     shapes = [(480, 640), (480, 752), (600, 960), (720, 1280), (33, 47), (1080, 1920)]
     imgs = [texture(h, w, 20 + i) for i, (h, w) in enumerate(shapes)]
